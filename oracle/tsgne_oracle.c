@@ -1,0 +1,421 @@
+/*
+ * FP64 CPU oracle for the t-SGNE optimisation loop.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it, to check the HIP library against a plain, slow,
+ * obviously correct implementation.  It shares no code, header, table or
+ * helper with the HIP library.
+ *
+ * Everything is computed in double precision from FP32 inputs promoted
+ * exactly.  Each function cites the passage of the paper (Li, Xiao, Zhou,
+ * "Efficiently Visualizing Large Graphs", arXiv 2310.11186) it follows; where
+ * the paper is silent the reading taken is named in the comment.
+ *
+ * Pins: every function here is pinned by tests that do not re-type its
+ * formula (finite differences, closed forms, brute force, invariants); the
+ * momentum/gains update is pinned only by a hand-computed step because the
+ * paper gives no optimiser.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_EGRAPH (-2)
+#define ORACLE_ENOMEM (-3)
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void oracle_set_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Graph: G = (V, E) undirected and unweighted (§2, problem statement). */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t r, c;
+} pair32;
+
+static int cmp_pair(const void* a, const void* b) {
+  const pair32* x = (const pair32*)a;
+  const pair32* y = (const pair32*)b;
+  if (x->r != y->r) return x->r < y->r ? -1 : 1;
+  if (x->c != y->c) return x->c < y->c ? -1 : 1;
+  return 0;
+}
+
+/*
+ * Canonical CSR of an undirected edge list (§2: G undirected, unweighted).
+ * Self-loops are dropped, each edge {u,v} becomes (u,v) and (v,u), entries
+ * are sorted by (row, col) and duplicates removed.  col must hold 2*m
+ * entries; row_ptr n+1.  Returns ORACLE_EINVAL on an out-of-range endpoint.
+ */
+int oracle_csr_from_edges(int32_t n, int64_t m, const int32_t* uv, int32_t* row_ptr, int32_t* col,
+                          int64_t* nnz_out) {
+  if (n < 0 || m < 0) return ORACLE_EINVAL;
+  pair32* e = (pair32*)malloc(sizeof(pair32) * (size_t)(2 * m + 1));
+  if (!e) return ORACLE_ENOMEM;
+  int64_t k = 0;
+  for (int64_t t = 0; t < m; ++t) {
+    int32_t u = uv[2 * t], v = uv[2 * t + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n) {
+      free(e);
+      return ORACLE_EINVAL;
+    }
+    if (u == v) continue;
+    e[k].r = u; e[k].c = v; ++k;
+    e[k].r = v; e[k].c = u; ++k;
+  }
+  qsort(e, (size_t)k, sizeof(pair32), cmp_pair);
+  int64_t w = 0;
+  for (int64_t t = 0; t < k; ++t) {
+    if (w > 0 && e[t].r == e[w - 1].r && e[t].c == e[w - 1].c) continue;
+    e[w++] = e[t];
+  }
+  for (int32_t i = 0; i <= n; ++i) row_ptr[i] = 0;
+  for (int64_t t = 0; t < w; ++t) row_ptr[e[t].r + 1] += 1;
+  for (int32_t i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+  for (int64_t t = 0; t < w; ++t) col[t] = e[t].c;
+  *nnz_out = w;
+  free(e);
+  return ORACLE_OK;
+}
+
+/* Position of column j in row i (ascending), or -1. */
+static int64_t find_in_row(const int32_t* row_ptr, const int32_t* col, int32_t i, int32_t j) {
+  int64_t lo = row_ptr[i], hi = row_ptr[i + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (col[mid] == j) return mid;
+    if (col[mid] < j) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/*
+ * Checks that the CSR is canonical (row_ptr monotone from 0, columns in range,
+ * strictly ascending per row, no self-loops) and structurally symmetric, and
+ * gives each entry e = (i, j) the position of (j, i).  The neighbourhood graph
+ * of t-SGNE is built from G itself (§2.2, eq. (7)), so it inherits G's symmetry.
+ */
+int oracle_mirror(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, int32_t* mirror) {
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) return ORACLE_EGRAPH;
+  for (int32_t i = 0; i < n; ++i) {
+    if (row_ptr[i + 1] < row_ptr[i]) return ORACLE_EGRAPH;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int32_t j = col[e];
+      if (j < 0 || j >= n || j == i) return ORACLE_EGRAPH;
+      if (e > row_ptr[i] && col[e - 1] >= j) return ORACLE_EGRAPH;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int64_t p = find_in_row(row_ptr, col, col[e], i);
+      if (p < 0) return ORACLE_EGRAPH;
+      mirror[e] = (int32_t)p;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Affinities P (§2.1, eqs. (2)-(3)) over graph neighbours (§2.2).      */
+/* ------------------------------------------------------------------ */
+
+/* D_e = ||x_i - x_j||^2 for each CSR entry, the squared distance of eq. (2). */
+void oracle_edge_sqdist(int32_t n, const int32_t* row_ptr, const int32_t* col, const float* X, int32_t d,
+                        double* D) {
+  for (int32_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int32_t j = col[e];
+      double s = 0.0;
+      for (int32_t k = 0; k < d; ++k) {
+        double t = (double)X[(int64_t)i * d + k] - (double)X[(int64_t)j * d + k];
+        s += t * t;
+      }
+      D[e] = s;
+    }
+  }
+}
+
+/*
+ * Entropy (natural log) of the row distribution p_j = exp(-beta*delta_j)/S,
+ * with delta_j = D_j - D_min >= 0.  H = log S + beta * sum(delta_j e_j) / S.
+ * Shifting by D_min leaves p unchanged (eq. (2) is a ratio).
+ */
+static double row_entropy(const double* delta, int64_t deg, double beta) {
+  double S = 0.0, T = 0.0;
+  for (int64_t k = 0; k < deg; ++k) {
+    double ek = exp(-beta * delta[k]);
+    S += ek;
+    T += delta[k] * ek;
+  }
+  return log(S) + beta * T / S;
+}
+
+/*
+ * Conditional affinities p_{j|i} of eq. (2), restricted to the graph
+ * neighbours N(i) (§2.2), with 1/(2 sigma_i^2) written as beta_i and chosen by
+ * binary search so that the perplexity equals perp (§2.1).
+ *
+ * Readings where the paper is silent:
+ *  - entropy in nats with target log(perp) (equivalent to 2^H in bits);
+ *  - deg_i == 0: empty row, beta_i = 0;
+ *  - deg_i <= perp: the target is unreachable (max entropy is log deg_i), so
+ *    the row is uniform, the beta -> 0 limit; beta_i = 0;
+ *  - m = number of neighbours at the minimum distance; if m >= perp the row is
+ *    uniform over those m (the beta -> infinity limit); beta_i = +inf;
+ *  - otherwise the bracket starts at beta = 1/mean(delta), doubles or halves
+ *    until it straddles the target, then bisects until the relative width is
+ *    at most 1e-13 (or 200 halvings); beta_i is the midpoint.
+ * pcond is aligned with col; beta has n entries.
+ */
+void oracle_calibrate(int32_t n, const int32_t* row_ptr, const double* D, double perp, double* pcond,
+                      double* beta) {
+  const double target = log(perp);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t b = row_ptr[i], deg = row_ptr[i + 1] - row_ptr[i];
+    if (deg == 0) {
+      beta[i] = 0.0;
+      continue;
+    }
+    if ((double)deg <= perp) {
+      for (int64_t k = 0; k < deg; ++k) pcond[b + k] = 1.0 / (double)deg;
+      beta[i] = 0.0;
+      continue;
+    }
+    double dmin = D[b];
+    for (int64_t k = 1; k < deg; ++k)
+      if (D[b + k] < dmin) dmin = D[b + k];
+    int64_t m = 0;
+    for (int64_t k = 0; k < deg; ++k)
+      if (D[b + k] == dmin) ++m;
+    if ((double)m >= perp) {
+      for (int64_t k = 0; k < deg; ++k) pcond[b + k] = (D[b + k] == dmin) ? 1.0 / (double)m : 0.0;
+      beta[i] = INFINITY;
+      continue;
+    }
+    double* delta = (double*)malloc(sizeof(double) * (size_t)deg);
+    double mean = 0.0;
+    for (int64_t k = 0; k < deg; ++k) {
+      delta[k] = D[b + k] - dmin;
+      mean += delta[k];
+    }
+    mean /= (double)deg;
+    double b0 = 1.0 / mean, lo, hi;
+    if (row_entropy(delta, deg, b0) > target) {
+      lo = b0;
+      hi = 2.0 * b0;
+      while (row_entropy(delta, deg, hi) > target) {
+        lo = hi;
+        hi *= 2.0;
+      }
+    } else {
+      hi = b0;
+      lo = 0.5 * b0;
+      while (row_entropy(delta, deg, lo) <= target) {
+        hi = lo;
+        lo *= 0.5;
+      }
+    }
+    for (int it = 0; it < 200 && (hi - lo) > 1e-13 * hi; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (row_entropy(delta, deg, mid) > target) lo = mid; else hi = mid;
+    }
+    double bt = 0.5 * (lo + hi);
+    double S = 0.0;
+    for (int64_t k = 0; k < deg; ++k) S += exp(-bt * delta[k]);
+    for (int64_t k = 0; k < deg; ++k) pcond[b + k] = exp(-bt * delta[k]) / S;
+    beta[i] = bt;
+    free(delta);
+  }
+}
+
+/*
+ * Joint affinities of eq. (3): p_ij = (p_{j|i} + p_{i|j}) / S on the CSR
+ * pattern.  Reading: the paper's 2n assumes every row sums to one; isolated
+ * nodes have empty rows, so S = 2 * (number of non-isolated nodes), which
+ * makes P sum to one and equals 2n when no node is isolated.
+ */
+int oracle_symmetrise(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* pcond, double* P) {
+  int64_t nonisolated = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (row_ptr[i + 1] > row_ptr[i]) ++nonisolated;
+  double S = 2.0 * (double)nonisolated;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int64_t t = find_in_row(row_ptr, col, col[e], i);
+      if (t < 0) return ORACLE_EGRAPH;
+      P[e] = (pcond[e] + pcond[t]) / S;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/* Whole affinity construction: eq. (2) over N(i), perplexity search, eq. (3). */
+int oracle_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const float* X, int32_t d,
+                   double perp, double* P, double* beta) {
+  if (perp <= 1.0 || d <= 0) return ORACLE_EINVAL;
+  int32_t* mirror = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+  int rc = oracle_mirror(n, nnz, row_ptr, col, mirror);
+  free(mirror);
+  if (rc != ORACLE_OK) return rc;
+  double* D = (double*)malloc(sizeof(double) * (size_t)(nnz + 1));
+  double* pc = (double*)malloc(sizeof(double) * (size_t)(nnz + 1));
+  oracle_edge_sqdist(n, row_ptr, col, X, d, D);
+  oracle_calibrate(n, row_ptr, D, perp, pc, beta);
+  rc = oracle_symmetrise(n, row_ptr, col, pc, P);
+  free(D);
+  free(pc);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Objective and gradient (§2.1, eqs. (4)-(5)).                        */
+/* ------------------------------------------------------------------ */
+
+static double kernel_w(const double* Y, int32_t i, int32_t j) {
+  double dx = Y[2 * i] - Y[2 * j], dy = Y[2 * i + 1] - Y[2 * j + 1];
+  return 1.0 / (1.0 + dx * dx + dy * dy);
+}
+
+/* Z = sum over ordered pairs k != l of (1 + ||y_k - y_l||^2)^-1, the
+ * denominator of eq. (4).  Row sums are formed independently and added in row
+ * order, so the result does not depend on the thread count. */
+double oracle_Z(int32_t n, const double* Y) {
+  double* rs = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int32_t j = 0; j < n; ++j)
+      if (j != i) s += kernel_w(Y, i, j);
+    rs[i] = s;
+  }
+  double Z = 0.0;
+  for (int32_t i = 0; i < n; ++i) Z += rs[i];
+  free(rs);
+  return Z;
+}
+
+/*
+ * Gradient of eq. (5) with respect to y_i (reading: the paper states only the
+ * objective; this is its analytic gradient, pinned by finite differences):
+ *   g_i = 4 * sum_{j != i} (alpha * p_ij - q_ij) * w_ij * (y_i - y_j),
+ * w_ij = (1 + ||y_i - y_j||^2)^-1, q_ij = w_ij / Z.  alpha is the early
+ * exaggeration factor applied to P (alpha = 1 gives the plain gradient).
+ * p_ij vanishes off the CSR pattern, so the attractive part runs over the
+ * stored entries and the repulsive part over all j != i.
+ * Rows listed in `rows` (count nrows) are computed; rows == NULL means all.
+ * Z is always the full all-pairs sum.
+ */
+void oracle_gradient_rows(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y,
+                          double alpha, const int32_t* rows, int32_t nrows, double* g, double* Z_out) {
+  double Z = oracle_Z(n, Y);
+  int32_t count = rows ? nrows : n;
+#pragma omp parallel for schedule(static)
+  for (int32_t t = 0; t < count; ++t) {
+    int32_t i = rows ? rows[t] : t;
+    double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int32_t j = col[e];
+      double w = kernel_w(Y, i, j);
+      ax += alpha * P[e] * w * (Y[2 * i] - Y[2 * j]);
+      ay += alpha * P[e] * w * (Y[2 * i + 1] - Y[2 * j + 1]);
+    }
+    for (int32_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double w = kernel_w(Y, i, j);
+      double q = w / Z;
+      rx += q * w * (Y[2 * i] - Y[2 * j]);
+      ry += q * w * (Y[2 * i + 1] - Y[2 * j + 1]);
+    }
+    g[2 * t] = 4.0 * (ax - rx);
+    g[2 * t + 1] = 4.0 * (ay - ry);
+  }
+  if (Z_out) *Z_out = Z;
+}
+
+void oracle_gradient(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y,
+                     double alpha, double* g, double* Z_out) {
+  oracle_gradient_rows(n, row_ptr, col, P, Y, alpha, NULL, n, g, Z_out);
+}
+
+/* KL(P || Q) of eq. (5) with q_ij = w_ij / Z; terms with p_ij = 0 vanish. */
+double oracle_kl(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y) {
+  double Z = oracle_Z(n, Y);
+  double kl = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      if (P[e] <= 0.0) continue;
+      double q = kernel_w(Y, i, col[e]) / Z;
+      kl += P[e] * log(P[e] / q);
+    }
+  }
+  return kl;
+}
+
+/* ------------------------------------------------------------------ */
+/* Optimiser.  The paper defers it to the original t-SNE article; the  */
+/* reading is gradient descent with momentum and per-coordinate gains. */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One update per coordinate c (reading; parity pinned only by a hand step):
+ *   gain_c <- gain_c + 0.2 if g_c * u_c < 0, else 0.8 * gain_c;
+ *   gain_c <- max(gain_c, min_gain);
+ *   u_c    <- momentum * u_c - eta * gain_c * g_c;
+ *   y_c    <- y_c + u_c.
+ */
+void oracle_update(int32_t n, double* Y, double* U, double* gains, const double* g, double momentum, double eta,
+                   double min_gain) {
+  for (int64_t c = 0; c < 2 * (int64_t)n; ++c) {
+    if (g[c] * U[c] < 0.0)
+      gains[c] += 0.2;
+    else
+      gains[c] *= 0.8;
+    if (gains[c] < min_gain) gains[c] = min_gain;
+    U[c] = momentum * U[c] - eta * gains[c] * g[c];
+    Y[c] += U[c];
+  }
+}
+
+/*
+ * Steps t = t0 .. t0+n_steps-1 of the loop: exaggeration alpha = ee and
+ * momentum m_early while t < t_ee, then 1 and m_late.  Y, U, gains are updated
+ * in place.  If kl_trace is given, the KL at the state after each step whose
+ * index+1 is a multiple of kl_every is written in order.
+ */
+void oracle_run(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, double* Y, double* U,
+                double* gains, int32_t t0, int32_t n_steps, double ee, int32_t t_ee, double m_early, double m_late,
+                double eta, double min_gain, int32_t kl_every, double* kl_trace) {
+  double* g = (double*)malloc(sizeof(double) * (size_t)(2 * (int64_t)n + 2));
+  int32_t nk = 0;
+  for (int32_t t = t0; t < t0 + n_steps; ++t) {
+    double alpha = t < t_ee ? ee : 1.0;
+    double mom = t < t_ee ? m_early : m_late;
+    oracle_gradient(n, row_ptr, col, P, Y, alpha, g, NULL);
+    oracle_update(n, Y, U, gains, g, mom, eta, min_gain);
+    if (kl_trace && kl_every > 0 && (t + 1) % kl_every == 0) kl_trace[nk++] = oracle_kl(n, row_ptr, col, P, Y);
+  }
+  free(g);
+}

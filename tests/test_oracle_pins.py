@@ -1,0 +1,369 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: hand-worked closed forms of
+eqs. (3)-(5) (tests/golden/hand_cases.json), finite differences of the
+objective, brute-force affinities by an independent root finder, special
+cases with closed forms, and invariants of the mathematics.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import oracle
+from paper_2310_11186_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")
+
+
+def frac(s: str) -> float:
+    return float(Fraction(s))
+
+
+def rows_of(row_ptr):
+    return np.repeat(np.arange(row_ptr.shape[0] - 1), np.diff(row_ptr))
+
+
+def entry(row_ptr, col, i, j):
+    seg = col[row_ptr[i]:row_ptr[i + 1]]
+    k = np.searchsorted(seg, j)
+    assert k < seg.shape[0] and seg[k] == j
+    return row_ptr[i] + k
+
+
+# ---------------------------------------------------------------------------
+# Hand-worked cases (closed forms of eqs. (3)-(5))
+# ---------------------------------------------------------------------------
+
+def _cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_hand_cases(case):
+    n = case["n"]
+    row_ptr, col = oracle.csr_from_edges(n, np.array(case["edges"]))
+    X = np.random.default_rng(0).standard_normal((n, 5)).astype(np.float32)
+    P, beta = oracle.build_P(row_ptr, col, X, 30.0)
+    assert col.shape[0] == len(case["P"])
+    for key, val in case["P"].items():
+        i, j = map(int, key.split(","))
+        assert P[entry(row_ptr, col, i, j)] == pytest.approx(frac(val), rel=1e-15)
+    Y = np.array(case["Y"], np.float64)
+    g, Z = oracle.gradient(row_ptr, col, P, Y, 1.0)
+    if case["Z"] == "2/(1+d2)":
+        d2 = float(((Y[0] - Y[1]) ** 2).sum())
+        assert Z == pytest.approx(2.0 / (1.0 + d2), rel=1e-15)
+    else:
+        assert Z == pytest.approx(frac(case["Z"]), rel=1e-14)
+    kl_expected = sum(frac(c) * math.log(frac(r)) for c, r in case["kl_terms"])
+    assert oracle.kl(row_ptr, col, P, Y) == pytest.approx(kl_expected, rel=1e-13, abs=1e-15)
+    g_expected = np.array([[frac(a), frac(b)] for a, b in case["grad"]])
+    np.testing.assert_allclose(g, g_expected, rtol=1e-13, atol=1e-15)
+
+
+def test_Z_all_coincident_positions():
+    # Y == 0: every w_ij = 1, so Z = n(n-1) exactly (denominator of eq. (4)).
+    for n in (1, 2, 7, 64):
+        assert oracle.Z(np.zeros((n, 2))) == float(n * (n - 1))
+
+
+# ---------------------------------------------------------------------------
+# Gradient: finite differences of the objective
+# ---------------------------------------------------------------------------
+
+def _small_graph(n, avg_deg, seed, d=6):
+    g = synth.small_sbm(n, 2, avg_deg, d, seed)
+    row_ptr, col = oracle.csr_from_edges(n, g.edges)
+    return g, row_ptr, col
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_gradient_matches_finite_differences_of_kl(seed):
+    g, row_ptr, col = _small_graph(10, 5.0, seed)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 2.5)     # low perplexity: the search runs on most rows
+    Y = np.random.default_rng(seed).standard_normal((10, 2))
+    grad, _ = oracle.gradient(row_ptr, col, P, Y, 1.0)
+    h = 1e-6
+    fd = np.zeros_like(Y)
+    for i in range(Y.shape[0]):
+        for c in range(2):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            fd[i, c] = (oracle.kl(row_ptr, col, P, Yp) - oracle.kl(row_ptr, col, P, Ym)) / (2 * h)
+    np.testing.assert_allclose(grad, fd, rtol=1e-6, atol=1e-9)
+
+
+def test_exaggerated_gradient_matches_finite_differences():
+    # With P scaled by alpha the gradient is that of F = -alpha sum p log w + log Z
+    # (KL up to constants when alpha = 1); F is evaluated here directly.
+    g, row_ptr, col = _small_graph(9, 4.0, 11)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 2.0)
+    rows = rows_of(row_ptr)
+    alpha = 12.0
+
+    def F(Y):
+        d2 = ((Y[rows] - Y[col]) ** 2).sum(1)
+        diff = Y[:, None, :] - Y[None, :, :]
+        W = 1.0 / (1.0 + (diff ** 2).sum(-1))
+        np.fill_diagonal(W, 0.0)
+        return alpha * float((P * np.log1p(d2)).sum()) + math.log(W.sum())
+
+    Y = np.random.default_rng(5).standard_normal((9, 2)) * 2.0
+    grad, _ = oracle.gradient(row_ptr, col, P, Y, alpha)
+    h = 1e-6
+    for i in range(9):
+        for c in range(2):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            assert grad[i, c] == pytest.approx((F(Yp) - F(Ym)) / (2 * h), rel=1e-6, abs=1e-9)
+
+
+def test_gradient_invariants():
+    g, row_ptr, col = _small_graph(40, 6.0, 7)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 5.0)
+    Y = np.random.default_rng(1).standard_normal((40, 2)) * 3.0
+    for alpha in (1.0, 12.0):
+        grad, Z = oracle.gradient(row_ptr, col, P, Y, alpha)
+        # pairwise forces are antisymmetric, so they sum to zero
+        assert np.abs(grad.sum(0)).max() < 1e-14 * max(1.0, np.abs(grad).sum())
+        # translation invariance
+        g2, Z2 = oracle.gradient(row_ptr, col, P, Y + np.array([3.5, -7.25]), alpha)
+        np.testing.assert_allclose(g2, grad, rtol=1e-9, atol=1e-13)
+        assert Z2 == pytest.approx(Z, rel=1e-12)
+        # rotation equivariance
+        th = 0.7
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+        g3, _ = oracle.gradient(row_ptr, col, P, Y @ R.T, alpha)
+        np.testing.assert_allclose(g3, grad @ R.T, rtol=1e-9, atol=1e-13)
+
+
+def test_two_nodes_are_stationary():
+    row_ptr, col = oracle.csr_from_edges(2, np.array([[0, 1]]))
+    P, _ = oracle.build_P(row_ptr, col, np.zeros((2, 3), np.float32), 30.0)
+    for Y in (np.array([[0.0, 0.0], [1.0, 2.0]]), np.array([[-3.0, 5.0], [0.1, 0.2]])):
+        grad, _ = oracle.gradient(row_ptr, col, P, Y)
+        assert np.abs(grad).max() < 1e-16
+        assert abs(oracle.kl(row_ptr, col, P, Y)) < 1e-16
+
+
+def test_kl_translation_invariant():
+    g, row_ptr, col = _small_graph(30, 5.0, 9)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 4.0)
+    Y = np.random.default_rng(2).standard_normal((30, 2))
+    a = oracle.kl(row_ptr, col, P, Y)
+    b = oracle.kl(row_ptr, col, P, Y - np.array([100.0, 0.5]))
+    assert a == pytest.approx(b, rel=1e-10)
+    assert a > 0
+
+
+# ---------------------------------------------------------------------------
+# Affinities: brute force with an independent root finder, closed forms
+# ---------------------------------------------------------------------------
+
+def brute_conditional(Dn, perp):
+    """p_{j|i} over one neighbour set by solving 2^{H_bits} = perp for sigma
+    with Brent's method on log(sigma) (eq. (2) in its sigma form)."""
+    Dn = np.asarray(Dn, np.float64)
+    deg = Dn.shape[0]
+    if deg <= perp:
+        return np.full(deg, 1.0 / deg)
+
+    def p_of(log_sigma):
+        s2 = math.exp(2 * log_sigma)
+        a = -(Dn - Dn.min()) / (2 * s2)
+        e = np.exp(a)
+        return e / e.sum()
+
+    def f(log_sigma):
+        p = p_of(log_sigma)
+        nz = p[p > 0]
+        return 2.0 ** (-(nz * np.log2(nz)).sum()) - perp
+
+    root = brentq(f, -40.0, 40.0, xtol=1e-15, rtol=1e-15, maxiter=500)
+    return p_of(root)
+
+
+@pytest.mark.parametrize("perp", [1.5, 2.5, 3.7, 30.0])
+def test_affinities_against_brute_force(perp):
+    g = synth.small_sbm(12, 2, 6.0, 4, seed=21)
+    row_ptr, col = oracle.csr_from_edges(12, g.edges)
+    X = g.X.astype(np.float64)
+    n = 12
+    Pc = np.zeros((n, n))
+    for i in range(n):
+        nb = col[row_ptr[i]:row_ptr[i + 1]]
+        if nb.size == 0:
+            continue
+        Dn = ((X[i] - X[nb]) ** 2).sum(1)
+        Pc[i, nb] = brute_conditional(Dn, perp)
+    nonisolated = int((np.diff(row_ptr) > 0).sum())
+    Pd = (Pc + Pc.T) / (2 * nonisolated)
+    P, _ = oracle.build_P(row_ptr, col, g.X, perp)
+    rows = rows_of(row_ptr)
+    np.testing.assert_allclose(P, Pd[rows, col], rtol=2e-9, atol=1e-15)
+    # and nothing outside the pattern
+    mask = np.zeros((n, n), bool)
+    mask[rows, col] = True
+    assert np.all(Pd[~mask] == 0)
+
+
+def test_degree_two_row_closed_form():
+    # A node with two neighbours at squared distances D1 < D2 and 1 < perp < 2:
+    # its row is (p, 1-p) with binary entropy h(p) = ln perp, and
+    # beta = ln(p/(1-p)) / (D2 - D1).
+    X = np.array([[0, 0], [1, 0], [0, 2.0], [5, 5]], np.float32)
+    edges = np.array([[0, 1], [0, 2], [2, 3]])
+    row_ptr, col = oracle.csr_from_edges(4, edges)
+    D = oracle.edge_sqdist(row_ptr, col, X)
+    for perp in (1.2, 1.5, 1.9):
+        pc, beta = oracle.calibrate(row_ptr, D, perp)
+        p = brentq(lambda q: -(q * math.log(q) + (1 - q) * math.log(1 - q)) - math.log(perp), 0.5, 1 - 1e-15,
+                   xtol=1e-16, rtol=1e-15)
+        e01, e02 = entry(row_ptr, col, 0, 1), entry(row_ptr, col, 0, 2)
+        assert D[e01] == 1.0 and D[e02] == 4.0
+        assert pc[e01] == pytest.approx(p, rel=1e-11)
+        assert pc[e02] == pytest.approx(1 - p, rel=1e-9)
+        assert beta[0] == pytest.approx(math.log(p / (1 - p)) / 3.0, rel=1e-10)
+
+
+def test_affinity_invariants():
+    g = synth.small_sbm(300, 6, 9.0, 8, seed=4)
+    row_ptr, col = oracle.csr_from_edges(300, g.edges)
+    perp = 5.0
+    D = oracle.edge_sqdist(row_ptr, col, g.X)
+    pc, beta = oracle.calibrate(row_ptr, D, perp)
+    P = oracle.symmetrise(row_ptr, col, pc)
+    mir = oracle.mirror(row_ptr, col)
+    assert np.array_equal(P, P[mir])                       # symmetric bit for bit
+    assert P.sum() == pytest.approx(1.0, abs=1e-12)
+    deg = np.diff(row_ptr)
+    calibrated = 0
+    for i in range(300):
+        seg = pc[row_ptr[i]:row_ptr[i + 1]]
+        if deg[i] == 0:
+            continue
+        assert seg.sum() == pytest.approx(1.0, abs=1e-13)
+        if deg[i] <= perp:
+            assert np.all(seg == 1.0 / deg[i])
+        else:
+            calibrated += 1
+            H = -(seg[seg > 0] * np.log(seg[seg > 0])).sum()
+            assert H == pytest.approx(math.log(perp), abs=1e-10)
+    assert calibrated > 100
+
+
+def test_isolated_nodes_and_normaliser():
+    # nodes 3 and 5 are isolated: their rows are empty and S = 2 * 4
+    edges = np.array([[0, 1], [1, 2], [2, 4], [4, 0]])
+    row_ptr, col = oracle.csr_from_edges(6, edges)
+    X = np.random.default_rng(3).standard_normal((6, 3)).astype(np.float32)
+    P, _ = oracle.build_P(row_ptr, col, X, 30.0)
+    assert np.diff(row_ptr)[3] == 0 and np.diff(row_ptr)[5] == 0
+    assert P.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.all(P == 1.0 / 8.0)            # 4-cycle, all rows uniform 1/2: (1/2+1/2)/8
+
+
+def test_ties_at_minimum_distance():
+    # node 0 has 5 neighbours; 3 share the minimum distance; with perp <= 3
+    # the row is uniform over those three (beta -> infinity limit).
+    X = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [3, 0], [0, 4]], np.float32)
+    edges = np.array([[0, k] for k in range(1, 6)])
+    row_ptr, col = oracle.csr_from_edges(6, edges)
+    D = oracle.edge_sqdist(row_ptr, col, X)
+    pc, beta = oracle.calibrate(row_ptr, D, 2.5)
+    np.testing.assert_array_equal(pc[0:5], [1 / 3, 1 / 3, 1 / 3, 0, 0])
+    assert math.isinf(beta[0])
+    pc, beta = oracle.calibrate(row_ptr, D, 4.0)     # reachable: a finite beta
+    assert math.isfinite(beta[0]) and beta[0] > 0
+    H = -(pc[0:5] * np.log(pc[0:5])).sum()
+    assert H == pytest.approx(math.log(4.0), abs=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# CSR construction and mirror index
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_csr_against_dense_adjacency(seed):
+    rng = np.random.default_rng(seed)
+    n = 37
+    uv = rng.integers(0, n, size=(150, 2))      # includes self-loops and repeats
+    row_ptr, col = oracle.csr_from_edges(n, uv)
+    A = np.zeros((n, n), bool)
+    for u, v in uv:
+        if u != v:
+            A[u, v] = A[v, u] = True
+    r, c = np.nonzero(A)                          # row-major: sorted by (row, col)
+    assert np.array_equal(col, c)
+    assert np.array_equal(row_ptr, np.concatenate([[0], np.cumsum(A.sum(1))]))
+    mir = oracle.mirror(row_ptr, col)
+    rows = rows_of(row_ptr)
+    assert np.array_equal(col[mir], rows)
+    assert np.array_equal(rows[mir], col)
+    assert np.array_equal(mir[mir], np.arange(col.shape[0]))
+
+
+def test_mirror_rejects_non_canonical():
+    row_ptr = np.array([0, 1, 1], np.int32)
+    with pytest.raises(oracle.OracleError):
+        oracle.mirror(row_ptr, np.array([1], np.int32))          # (0,1) without (1,0)
+    with pytest.raises(oracle.OracleError):
+        oracle.mirror(np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32))   # repeated column
+    with pytest.raises(oracle.OracleError):
+        oracle.mirror(np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32))        # self-loops
+
+
+# ---------------------------------------------------------------------------
+# Update rule (reading: momentum + gains; the paper gives no optimiser)
+# ---------------------------------------------------------------------------
+
+def test_update_single_step_by_hand():
+    Y = np.array([[1.0, -2.0]])
+    U = np.array([[0.5, 0.25]])
+    gains = np.array([[1.0, 0.02]])
+    g = np.array([[-0.1, 0.4]])
+    Y1, U1, G1 = oracle.update(Y, U, gains, g, momentum=0.8, eta=10.0, min_gain=0.01)
+    # x: g*u = -0.05 < 0 -> gain 1.2; u = 0.4 + 1.2 = 1.6; y = 2.6
+    # y: g*u = 0.1 >= 0 -> gain 0.016; u = 0.2 - 0.064 = 0.136; y = -1.864
+    np.testing.assert_allclose(G1, [[1.2, 0.016]], rtol=1e-15)
+    np.testing.assert_allclose(U1, [[1.6, 0.136]], rtol=1e-14)
+    np.testing.assert_allclose(Y1, [[2.6, -1.864]], rtol=1e-14)
+    # zero product (first step, u = 0) shrinks the gain; the clamp holds min_gain
+    _, _, G2 = oracle.update(Y, np.zeros_like(U), np.array([[0.011, 1.0]]), g, 0.5, 1.0, 0.01)
+    np.testing.assert_allclose(G2, [[0.01, 0.8]], rtol=1e-15)
+
+
+def test_run_switches_exaggeration_and_momentum():
+    g, row_ptr, col = _small_graph(20, 5.0, 13)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 4.0)
+    Y0 = g.Y0.astype(np.float64) * 100
+    Y, U, G, _ = oracle.run(row_ptr, col, P, Y0, n_steps=4, early_exaggeration=4.0, exaggeration_iters=2,
+                            momentum_early=0.5, momentum_late=0.8, eta=20.0)
+    y, u, gn = Y0.copy(), np.zeros_like(Y0), np.ones_like(Y0)
+    for t in range(4):
+        gr, _ = oracle.gradient(row_ptr, col, P, y, 4.0 if t < 2 else 1.0)
+        y, u, gn = oracle.update(y, u, gn, gr, 0.5 if t < 2 else 0.8, 20.0)
+    np.testing.assert_array_equal(Y, y)
+    np.testing.assert_array_equal(U, u)
+    np.testing.assert_array_equal(G, gn)
+
+
+def test_oracle_threads_do_not_change_results():
+    g, row_ptr, col = _small_graph(200, 6.0, 17)
+    P, _ = oracle.build_P(row_ptr, col, g.X, 5.0)
+    Y = np.random.default_rng(4).standard_normal((200, 2))
+    k = oracle.num_threads()
+    oracle.set_threads(1)
+    a, za = oracle.gradient(row_ptr, col, P, Y)
+    oracle.set_threads(max(k, 2))
+    b, zb = oracle.gradient(row_ptr, col, P, Y)
+    oracle.set_threads(k)
+    assert np.array_equal(a, b) and za == zb
