@@ -1,0 +1,262 @@
+"""t-SGNE throughput benchmark on one MI355X.
+
+One step = one pass of the whole hot path over one graph: affinities
+(tsgne_build_P), n_iter optimisation steps (tsgne_run: repulsion + Z,
+attraction, update) and the final KL (tsgne_kl).  Inputs are synthetic and
+already resident in HBM when the timed region starts.  The default workload
+is the 300,000-node / 1,000,000-edge DC-SBM with 128-dim embeddings and 1000
+iterations.
+
+value = pair interactions per second over the whole job
+      = steps * n_iter * n(n-1) / elapsed.
+
+Prints one JSON line (rank 0).  Also reports the roofline of the dominant
+kernel (the repulsion, timed with HIP events on its own stream) and the FP64
+oracle timed on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FMA)
+FLOP_PER_PAIR = 13                # algorithmic flops per ordered pair of the repulsion
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("step.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2310_11186_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per repulsion launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, "repulsion_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def snowball(n: int, edges, size: int, seed: int):
+    """Node set of a BFS from seeded roots until `size` nodes (a sample of the
+    graph that keeps its local density)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    from collections import deque
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    seen = np.zeros(n, bool)
+    order = []
+    while len(order) < size:
+        root = int(rng.integers(0, n))
+        if seen[root]:
+            continue
+        seen[root] = True
+        q = deque([root])
+        while q and len(order) < size:
+            u = q.popleft()
+            order.append(u)
+            for v in adj[u]:
+                if not seen[v]:
+                    seen[v] = True
+                    q.append(v)
+    return np.array(sorted(order[:size]), np.int64)
+
+
+def cpu_baseline(gi, n_iter_total: int, exaggeration_iters: int, perplexity: float, budget_s: float):
+    """FP64 oracle on the host: optimisation steps on a 20,000-node snowball
+    sample of the same graph, timed until ~budget_s seconds have passed."""
+    import numpy as np
+
+    import oracle
+    size = min(20_000, gi.n)
+    nodes = snowball(gi.n, gi.edges, size, seed=1)
+    remap = -np.ones(gi.n, np.int64)
+    remap[nodes] = np.arange(size)
+    e = remap[gi.edges.astype(np.int64)]
+    e = e[(e[:, 0] >= 0) & (e[:, 1] >= 0)]
+    rp, col = oracle.csr_from_edges(size, e)
+    P, _ = oracle.build_P(rp, col, gi.X[nodes], perplexity)
+    Y = gi.Y0[nodes].astype(np.float64)
+    U = np.zeros_like(Y)
+    G = np.ones_like(Y)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < n_iter_total:
+        Y, U, G, _ = oracle.run(rp, col, P, Y, U, G, t0=steps, n_steps=1, exaggeration_iters=exaggeration_iters,
+                                eta=max(size / 48.0, 50.0))
+        steps += 1
+    dt = time.perf_counter() - t0
+    pairs = steps * size * (size - 1)
+    return {
+        "value": pairs / dt,
+        "unit": "pair-interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "%d full FP64 oracle steps (all-pairs gradient + update) on a %d-node, %d-edge BFS snowball "
+                  "sample of the same graph, %.1f s" % (steps, size, e.shape[0], dt),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="dcsbm300k")
+    ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
+    ap.add_argument("--repulsion", default="auto", choices=["auto", "direct", "symmetric"])
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--precision", default="split", choices=["split", "fp32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scales HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the t-SGNE path here is single-GPU (multi-GPU sharding is a design "
+              "note, not built); got --gpus %d" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 5}), flush=True)
+        return 0
+
+    dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[args.workload]
+    n_iter = args.n_iter if args.n_iter is not None else wl.n_iter
+    t_ee = min(wl.exaggeration_iters, n_iter // 4) if args.n_iter is not None else wl.exaggeration_iters
+    log("generating %s" % wl.description)
+    gi = synth.make(args.workload)
+    rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
+    d_rp = torch.from_numpy(rp).to(dev)
+    d_col = torch.from_numpy(col).to(dev)
+    d_X = torch.from_numpy(gi.X).to(dev)
+    d_Y0 = torch.from_numpy(gi.Y0).to(dev)
+    Y = torch.empty_like(d_Y0)
+    rep = {"auto": tsgne.TSGNE_REPULSION_AUTO, "direct": tsgne.TSGNE_REPULSION_DIRECT,
+           "symmetric": tsgne.TSGNE_REPULSION_SYMMETRIC}[args.repulsion]
+    prec = tsgne.TSGNE_PREC_FP32 if args.precision == "fp32" else tsgne.TSGNE_PREC_SPLIT
+    params = tsgne.tsgne_params_default(exaggeration_iters=t_ee, early_exaggeration=wl.early_exaggeration,
+                                        repulsion=rep, tile_rows=args.tile_rows, precision=prec)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def one_step(timed_graphs=None):
+        g = tsgne.tsgne_build_P(d_rp, d_col, d_X, wl.perplexity, stream)
+        if timed_graphs is not None:
+            g.set_timing(True)
+        Y.copy_(d_Y0)
+        tsgne.tsgne_run(g, Y, n_iter, params, stream)
+        kl = tsgne.tsgne_kl(g, Y, stream)
+        if timed_graphs is not None:
+            timed_graphs.append(g.timing())
+        g.close()
+        return kl
+
+    for w in range(args.warmup):
+        kl = one_step()
+        log("warmup %d/%d done (KL %.4f)" % (w + 1, args.warmup, kl))
+
+    timings = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kls = []
+    for k in range(args.steps):
+        kls.append(one_step(timings))
+        log("step %d/%d done (KL %.4f, %.1f s elapsed)" % (k + 1, args.steps, kls[-1], time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    n = gi.n
+    pairs_per_iter = n * (n - 1)
+    value = args.steps * n_iter * pairs_per_iter / elapsed
+    rep_ms = sum(t["repulsion"][0] for t in timings)
+    rep_launches = sum(t["repulsion"][1] for t in timings)
+    avg_rep_s = rep_ms / max(rep_launches, 1) / 1e3
+    achieved_tflops = FLOP_PER_PAIR * pairs_per_iter / avg_rep_s / 1e12 if rep_launches else None
+    phase_avg_ms = {}
+    for name in tsgne.TSGNE_PHASES:
+        tot = sum(t[name][0] for t in timings)
+        cnt = sum(t[name][1] for t in timings)
+        phase_avg_ms[name] = round(tot / cnt, 4) if cnt else None
+
+    result = {
+        "metric": "t-SGNE pair-interactions/s at 300K nodes (% FP32 peak)",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == tsgne.TSGNE_PREC_FP32 else "f32 (FP64 Z/KL/cross-tile sums)",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "description": wl.description, "nodes": n,
+            "edges": int(gi.edges.shape[0]), "d": gi.d, "n_iter": n_iter, "exaggeration_iters": t_ee,
+            "perplexity": wl.perplexity, "repulsion": args.repulsion, "precision": args.precision,
+            "step": "build_P + n_iter optimisation steps + KL",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_repulse (all-pairs repulsion + Z partials)",
+            "achieved": achieved_tflops,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS if achieved_tflops else None,
+            "traffic": measured_traffic(args.workload),
+            "flop_per_launch": FLOP_PER_PAIR * pairs_per_iter,
+            "avg_launch_ms": avg_rep_s * 1e3,
+            "launches": rep_launches,
+        },
+        "phase_avg_ms": phase_avg_ms,
+        "final_kl": kls[-1] if kls else None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (~%.0f s)" % args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(gi, n_iter, t_ee, wl.perplexity, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,221 @@
+/*
+ * tsgne.h -- C-ABI of the MI355X (gfx950) t-SGNE optimisation loop.
+ *
+ * The library turns a graph G = (V, E) (undirected, unweighted, |V| = n) and a
+ * node embedding X = {x_i in R^d} into a 2-D layout Y = {y_i in R^2}, the
+ * dimension-reduction half of GD = DR o GE (Li, Xiao, Zhou, "Efficiently
+ * Visualizing Large Graphs", arXiv 2310.11186, section 2, eq. (1)).  The
+ * affinities P follow section 2.1, eqs. (2)-(3), restricted to each node's
+ * graph neighbours as t-SGNE prescribes (section 2.2, eq. (7)); the layout
+ * minimises KL(P || Q) of eq. (5) with the Student-t Q of eq. (4).
+ *
+ * Conventions for every call:
+ *  - Pointers ending in _d are device pointers (HBM of the current HIP
+ *    device); pointers ending in _h are host pointers.  The caller owns every
+ *    pointer it passes; the library only reads or writes it during the call
+ *    (device writes complete in stream order).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it.  Calls marked "synchronising" block until
+ *    their work on `stream` has finished.
+ *  - Layouts: X is float32 [n][d] row-major; Y, upd, gains and grad are float32
+ *    [n][2] (x, y interleaved); the CSR is int32 row_ptr[n+1], col[nnz].
+ *  - Every call returns a tsgne_status; on failure tsgne_last_error() gives a
+ *    message (thread-local, valid until the next call on that thread).  No C++
+ *    exception crosses this boundary.  Errors raised by the device inside an
+ *    asynchronous call surface at the next synchronising call.
+ *  - A tsgne_graph* is owned by the library; release it with tsgne_graph_free.
+ *    Calls on one graph must not overlap (they share its workspace); different
+ *    graphs may be used concurrently from different threads.
+ */
+#ifndef TSGNE_H
+#define TSGNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TSGNE_API __attribute__((visibility("default")))
+#else
+#define TSGNE_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tsgne_status;
+#define TSGNE_OK 0
+#define TSGNE_E_INVAL (-1)     /* bad argument: null pointer, size, parameter */
+#define TSGNE_E_GRAPH (-2)     /* CSR not canonical (sorted, no self-loops) or not symmetric */
+#define TSGNE_E_NOMEM (-3)     /* device or host allocation failed */
+#define TSGNE_E_DEVICE (-4)    /* a HIP runtime call failed */
+#define TSGNE_E_NONFINITE (-5) /* a non-finite value appeared in the layout */
+#define TSGNE_E_BUSY (-6)      /* resource busy (queue full) */
+
+/* Precision modes of the per-step arithmetic. */
+#define TSGNE_PREC_SPLIT 0 /* FP32 pair arithmetic; FP64 for Z, cross-tile force sums, KL */
+#define TSGNE_PREC_FP32 1  /* everything FP32 (reported for comparison) */
+
+/* Repulsion kernel choice. */
+#define TSGNE_REPULSION_AUTO 0
+#define TSGNE_REPULSION_DIRECT 1    /* every ordered pair computed by its row's lane */
+#define TSGNE_REPULSION_SYMMETRIC 2 /* each unordered pair once, w_ij = w_ji shared */
+
+/*
+ * Optimiser parameters.  The paper names the objective (eq. (5)) but no
+ * optimiser; these are the usual t-SNE gradient-descent settings: early
+ * exaggeration of P, momentum, per-coordinate gains.
+ */
+typedef struct tsgne_params {
+  float early_exaggeration;   /* alpha applied to P while t < exaggeration_iters (default 12) */
+  int32_t exaggeration_iters; /* default 250; set n_iter/4 for other lengths */
+  float learning_rate;        /* eta; <= 0 selects max(n / (4 * early_exaggeration), 50) */
+  float momentum_early;       /* momentum while t < exaggeration_iters (default 0.5) */
+  float momentum_late;        /* momentum afterwards (default 0.8) */
+  float min_gain;             /* lower clamp of the gains (default 0.01) */
+  int32_t precision;          /* TSGNE_PREC_SPLIT (default) or TSGNE_PREC_FP32 */
+  int32_t kl_every;           /* tsgne_run: record KL after every kl_every-th step; 0 = off */
+  int32_t repulsion;          /* TSGNE_REPULSION_* (default AUTO = SYMMETRIC) */
+  int32_t tile_rows;          /* rows per lane of the repulsion tile: 4, 8, 16 or 0 = auto */
+} tsgne_params;
+
+typedef struct tsgne_graph tsgne_graph;
+
+/* Fills *p with the defaults listed above. */
+TSGNE_API void tsgne_params_default(tsgne_params* p);
+
+/* Message of the last failure on this thread ("" if none). */
+TSGNE_API const char* tsgne_last_error(void);
+
+/* Static name of a status code. */
+TSGNE_API const char* tsgne_status_string(tsgne_status s);
+
+/*
+ * Host helper: canonical symmetric CSR of an undirected edge list (section 2:
+ * G is undirected and unweighted).  uv_h holds m pairs (u, v) as int32[m][2];
+ * self-loops are dropped, each edge is stored both ways, columns are sorted
+ * ascending and repeats removed.  row_ptr_h must hold n+1 entries and col_h
+ * 2*m.  *nnz_out receives the number of stored entries.
+ * Errors: E_INVAL for null pointers, n < 0, m < 0, an endpoint outside [0, n)
+ * or a result with 2^31 or more entries.
+ */
+TSGNE_API tsgne_status tsgne_csr_from_edges(int32_t n, int64_t m, const int32_t* uv_h, int32_t* row_ptr_h, int32_t* col_h,
+                                  int64_t* nnz_out);
+
+/*
+ * Builds the joint affinities P of eq. (3) from the conditional affinities of
+ * eq. (2) over each node's graph neighbours (section 2.2), with the bandwidth
+ * of each row set by bisection so that its perplexity equals `perplexity`
+ * (section 2.1, entropy in nats against log(perplexity)).
+ *   n, nnz       -- number of nodes and of CSR entries (nnz < 2^31)
+ *   row_ptr_d    -- int32[n+1], col_d int32[nnz]: canonical symmetric CSR
+ *                   (row_ptr[0] = 0, row_ptr[n] = nnz, nondecreasing; columns
+ *                   in [0, n), strictly ascending per row, no self-loops,
+ *                   (i,j) stored iff (j,i) is)
+ *   X_d          -- float32[n][d], d >= 1
+ *   perplexity   -- > 1 (the paper's usual range is 5-50, 30 by default)
+ * Rows with deg <= perplexity are uniform (the target entropy is out of reach);
+ * isolated nodes get empty rows and P is normalised by 2 * (non-isolated
+ * nodes) so that it sums to one (eq. (3) writes 2n, which assumes no isolated
+ * node).  P is stored as float32 aligned with col, computed in FP64.
+ * The inputs are read during the call only: the graph keeps its own copies.
+ * Synchronising (the CSR check is read back).  *out receives a new graph.
+ * Errors: E_INVAL (null pointer, n < 1, nnz < 0, d < 1, perplexity <= 1 or
+ * not finite), E_GRAPH (CSR not canonical or not symmetric), E_NOMEM,
+ * E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d, const float* X_d,
+                           int32_t d, float perplexity, void* stream, tsgne_graph** out);
+
+/* Releases a graph and all device memory it holds.  NULL is accepted. */
+TSGNE_API tsgne_status tsgne_graph_free(tsgne_graph* g);
+
+/* Size of a graph: *n nodes, *nnz stored CSR entries (either may be NULL). */
+TSGNE_API tsgne_status tsgne_graph_info(const tsgne_graph* g, int32_t* n, int64_t* nnz);
+
+/*
+ * Copies the graph's device state to host buffers (any may be NULL):
+ * row_ptr_h int32[n+1], col_h int32[nnz], mirror_h int32[nnz] (position of
+ * entry (j,i) for entry (i,j)), P_h float32[nnz], beta_h float64[n] (the
+ * calibrated 1/(2 sigma_i^2); 0 for uniform rows, +inf for rows uniform over
+ * tied nearest neighbours).  Synchronising (on the null stream).
+ */
+TSGNE_API tsgne_status tsgne_graph_export(const tsgne_graph* g, int32_t* row_ptr_h, int32_t* col_h, int32_t* mirror_h,
+                                float* P_h, double* beta_h);
+
+/*
+ * Gradient of eq. (5) at Y with P scaled by alpha (early exaggeration):
+ *   g_i = 4 * sum_{j != i} (alpha * p_ij - q_ij) * w_ij * (y_i - y_j),
+ *   w_ij = (1 + ||y_i - y_j||^2)^-1,  q_ij = w_ij / Z,  Z = sum_{k != l} w_kl
+ * (eq. (4)).  Y_d float32[n][2] (read), grad_d float32[n][2] (written),
+ * Z_d float64[1] (written; may be NULL).  precision / repulsion / tile_rows are
+ * taken from p (NULL = defaults).  Asynchronous.
+ * Errors: E_INVAL, E_NOMEM (first use allocates the step workspace), E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_gradient(tsgne_graph* g, const float* Y_d, float alpha, const tsgne_params* p, float* grad_d,
+                            double* Z_d, void* stream);
+
+/*
+ * One optimisation step at index t: the gradient above with alpha =
+ * early_exaggeration if t < exaggeration_iters else 1, then per coordinate
+ *   gain <- (g * u < 0) ? gain + 0.2 : 0.8 * gain;  gain <- max(gain, min_gain);
+ *   u <- m_t * u - eta * gain * g;  y <- y + u
+ * with m_t = momentum_early if t < exaggeration_iters else momentum_late.
+ * Y_d, upd_d, gains_d: float32[n][2], updated in place (start with upd = 0,
+ * gains = 1).  grad_out_d (nullable) receives g at the input Y; Z_out_d
+ * (nullable, float64[1]) receives Z at the input Y.  Asynchronous.
+ * Errors: E_INVAL, E_NOMEM (first use allocates the step workspace), E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_step(tsgne_graph* g, float* Y_d, float* upd_d, float* gains_d, int32_t t, const tsgne_params* p,
+                        float* grad_out_d, double* Z_out_d, void* stream);
+
+/*
+ * n_iter steps t = 0 .. n_iter-1 from the layout in Y_d (float32[n][2], in:
+ * Y0, out: final layout), with internal upd (0) and gains (1).  Equals n_iter
+ * calls of tsgne_step bit for bit.  If p->kl_every > 0 and kl_trace_h is not
+ * NULL, kl_trace_h[k] receives the KL (eq. (5), unexaggerated P) after step
+ * (k+1)*kl_every - 1, for k < n_iter / kl_every.  Synchronising.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE (the final layout holds a
+ * NaN or infinity).
+ */
+TSGNE_API tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, const tsgne_params* p, double* kl_trace_h,
+                       void* stream);
+
+/*
+ * KL(P || Q) of eq. (5) at layout Y_d (float32[n][2]) with the unexaggerated
+ * P, accumulated in FP64.  Q's normaliser Z is recomputed at Y_d.
+ * *kl_h receives the value.  Synchronising.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, void* stream);
+
+/*
+ * Per-phase device timing of one graph's kernels, measured with HIP events
+ * recorded on the stream each kernel is launched on.  Phases:
+ */
+#define TSGNE_PHASE_REPULSION 0 /* all-pairs repulsion + Z partials (one launch per step) */
+#define TSGNE_PHASE_ZSUM 1      /* Z reduction */
+#define TSGNE_PHASE_ATTRACT 2   /* sparse attraction */
+#define TSGNE_PHASE_UPDATE 3    /* gradient combine + momentum/gains update */
+#define TSGNE_PHASE_KL 4        /* KL edge sum */
+#define TSGNE_NUM_PHASES 5
+
+typedef struct tsgne_timing {
+  double ms[TSGNE_NUM_PHASES];         /* summed device time per phase, milliseconds */
+  int64_t launches[TSGNE_NUM_PHASES];  /* number of timed launches per phase */
+} tsgne_timing;
+
+/*
+ * Turns per-phase timing of g on (enable != 0) or off and clears the totals.
+ * While on, each timed launch is bracketed by two events on its stream.
+ */
+TSGNE_API tsgne_status tsgne_graph_set_timing(tsgne_graph* g, int32_t enable);
+
+/* Totals since timing was enabled.  Synchronising (waits for the last event). */
+TSGNE_API tsgne_status tsgne_graph_timing(tsgne_graph* g, tsgne_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSGNE_H */

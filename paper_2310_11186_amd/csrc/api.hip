@@ -1,0 +1,598 @@
+// C-ABI entry points of the t-SGNE library (declared in include/tsgne.h):
+// argument validation, the graph handle and its device memory, the step
+// workspace, and the sequencing of the kernels on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace tsgne {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+namespace {
+
+tsgne_status fail(tsgne_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+tsgne_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? TSGNE_E_NOMEM : TSGNE_E_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TSGNE_HIP(call, what)                      \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_workspace(Workspace& ws) {
+  dfree(ws.items);
+  dfree(ws.part);
+  dfree(ws.zpart);
+  dfree(ws.zpart32);
+  dfree(ws.Z);
+  dfree(ws.attract);
+  dfree(ws.klpart);
+  dfree(ws.klout);
+  if (ws.pinned) (void)hipHostFree(ws.pinned);
+  ws.pinned = nullptr;
+  ws.plan = RepulsionPlan{};
+}
+
+void timer_destroy(PhaseTimer& t);
+
+void free_graph(tsgne_graph* g) {
+  if (!g) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(g->device);
+  free_workspace(g->ws);
+  timer_destroy(g->timer);
+  dfree(g->row_ptr);
+  dfree(g->col);
+  dfree(g->mirror);
+  dfree(g->row_of);
+  dfree(g->P);
+  dfree(g->beta);
+  dfree(g->heavy);
+  (void)hipSetDevice(cur);
+  delete g;
+}
+
+// Makes the graph's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// --- phase timing -----------------------------------------------------------
+
+hipEvent_t timer_event(PhaseTimer& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a timed launch; returns the index to close, or -1.
+int timer_begin(tsgne_graph* g, int phase, hipStream_t s) {
+  PhaseTimer& t = g->timer;
+  if (!t.enabled) return -1;
+  hipEvent_t a = timer_event(t), b = timer_event(t);
+  if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+    if (a) t.pool.push_back(a);
+    if (b) t.pool.push_back(b);
+    return -1;
+  }
+  t.pending.push_back({phase, a, b});
+  return (int)t.pending.size() - 1;
+}
+
+void timer_end(tsgne_graph* g, int idx, hipStream_t s) {
+  if (idx < 0) return;
+  (void)hipEventRecord(g->timer.pending[(size_t)idx].stop, s);
+}
+
+// Folds completed event pairs into the totals (waits for each stop event).
+hipError_t timer_resolve(tsgne_graph* g) {
+  PhaseTimer& t = g->timer;
+  hipError_t err = hipSuccess;
+  for (auto& p : t.pending) {
+    hipError_t e = hipEventSynchronize(p.stop);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.start, p.stop);
+    if (e == hipSuccess) {
+      t.ms[p.phase] += ms;
+      t.launches[p.phase] += 1;
+    } else if (err == hipSuccess) {
+      err = e;
+    }
+    t.pool.push_back(p.start);
+    t.pool.push_back(p.stop);
+  }
+  t.pending.clear();
+  return err;
+}
+
+void timer_destroy(PhaseTimer& t) {
+  for (auto& p : t.pending) {
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
+  }
+  for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+  t.pending.clear();
+  t.pool.clear();
+}
+
+struct Timed {
+  tsgne_graph* g;
+  int idx;
+  hipStream_t s;
+  Timed(tsgne_graph* g_, int phase, hipStream_t s_) : g(g_), idx(timer_begin(g_, phase, s_)), s(s_) {}
+  ~Timed() { timer_end(g, idx, s); }
+};
+
+tsgne_status validate_params(const tsgne_params* p) {
+  if (!std::isfinite(p->early_exaggeration) || p->early_exaggeration <= 0.f)
+    return fail(TSGNE_E_INVAL, "early_exaggeration must be finite and > 0");
+  if (p->exaggeration_iters < 0) return fail(TSGNE_E_INVAL, "exaggeration_iters must be >= 0");
+  if (!std::isfinite(p->learning_rate)) return fail(TSGNE_E_INVAL, "learning_rate must be finite");
+  if (!std::isfinite(p->momentum_early) || !std::isfinite(p->momentum_late) || p->momentum_early < 0.f ||
+      p->momentum_late < 0.f || p->momentum_early >= 1.f || p->momentum_late >= 1.f)
+    return fail(TSGNE_E_INVAL, "momentum must lie in [0, 1)");
+  if (!std::isfinite(p->min_gain) || p->min_gain < 0.f) return fail(TSGNE_E_INVAL, "min_gain must be >= 0");
+  if (p->precision != TSGNE_PREC_SPLIT && p->precision != TSGNE_PREC_FP32)
+    return fail(TSGNE_E_INVAL, "precision must be TSGNE_PREC_SPLIT or TSGNE_PREC_FP32");
+  if (p->kl_every < 0) return fail(TSGNE_E_INVAL, "kl_every must be >= 0");
+  if (p->repulsion < TSGNE_REPULSION_AUTO || p->repulsion > TSGNE_REPULSION_SYMMETRIC)
+    return fail(TSGNE_E_INVAL, "unknown repulsion variant");
+  if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16)
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 4, 8 or 16");
+  return TSGNE_OK;
+}
+
+float effective_eta(const tsgne_graph* g, const tsgne_params* p) {
+  if (p->learning_rate > 0.f) return p->learning_rate;
+  return std::max((float)g->n / (4.0f * p->early_exaggeration), 50.0f);
+}
+
+// Allocates (or re-plans) the per-step buffers for the requested tiling.
+tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p) {
+  Workspace& ws = g->ws;
+  const RepulsionPlan want = make_plan(g->n, p->tile_rows, p->repulsion);
+  const bool same = ws.part && ws.plan.R == want.R && ws.plan.variant == want.variant;
+  if (same) return TSGNE_OK;
+  if (ws.part) {
+    // Buffers may still be in use by queued work on any stream.
+    TSGNE_HIP(hipDeviceSynchronize(), "synchronise before re-planning");
+  }
+  free_workspace(ws);
+  ws.plan = want;
+  const RepulsionPlan& pl = ws.plan;
+  std::vector<int2> items;
+  items.reserve((size_t)pl.items);
+  for (int32_t a = 0; a < pl.nb; ++a)
+    for (int32_t b = (pl.variant == TSGNE_REPULSION_DIRECT ? 0 : a); b < pl.nb; ++b) items.push_back(make_int2(a, b));
+  const size_t part_len = (size_t)pl.nb * pl.nb * pl.T;
+  ws.kl_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1024, (g->nnz + 255) / 256));
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = dalloc(&ws.items, items.size());
+  if (e == hipSuccess) e = dalloc(&ws.part, part_len);
+  if (e == hipSuccess) e = dalloc(&ws.zpart, (size_t)pl.items);
+  if (e == hipSuccess) e = dalloc(&ws.zpart32, (size_t)pl.items);
+  if (e == hipSuccess) e = dalloc(&ws.Z, 1);
+  if (e == hipSuccess) e = dalloc(&ws.attract, (size_t)g->n);
+  if (e == hipSuccess) e = dalloc(&ws.klpart, (size_t)ws.kl_blocks);
+  if (e == hipSuccess) e = dalloc(&ws.klout, 1);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws.pinned), 64 * sizeof(double), 0);
+  if (e == hipSuccess)
+    e = hipMemcpy(ws.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_workspace(ws);
+    return hip_fail(e, "allocate step workspace");
+  }
+  return TSGNE_OK;
+}
+
+// Repulsion partials, Z, attraction: everything the gradient needs at Y.
+tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipStream_t s) {
+  const float2* Y2 = reinterpret_cast<const float2*>(Y);
+  {
+    Timed tm(g, TSGNE_PHASE_REPULSION, s);
+    TSGNE_HIP(launch_repulsion(g->ws, g->n, Y2, precision, s), "launch repulsion");
+  }
+  {
+    Timed tm(g, TSGNE_PHASE_ZSUM, s);
+    TSGNE_HIP(launch_zsum(g->ws, precision, s), "launch Z reduction");
+  }
+  {
+    Timed tm(g, TSGNE_PHASE_ATTRACT, s);
+    TSGNE_HIP(launch_attract(g, Y2, precision, s), "launch attraction");
+  }
+  return TSGNE_OK;
+}
+
+tsgne_status check_graph(const tsgne_graph* g) {
+  if (!g) return fail(TSGNE_E_INVAL, "graph is NULL");
+  return TSGNE_OK;
+}
+
+tsgne_status step_impl(tsgne_graph* g, float* Y, float* U, float* G, int32_t t, const tsgne_params* p, float* grad_out,
+                       double* Z_out, hipStream_t s) {
+  const bool early = t < p->exaggeration_iters;
+  const float alpha = early ? p->early_exaggeration : 1.0f;
+  const float mom = early ? p->momentum_early : p->momentum_late;
+  tsgne_status st = enqueue_forces(g, Y, p->precision, s);
+  if (st != TSGNE_OK) return st;
+  Timed tm(g, TSGNE_PHASE_UPDATE, s);
+  TSGNE_HIP(launch_update(g, reinterpret_cast<float2*>(Y), reinterpret_cast<float2*>(U), reinterpret_cast<float2*>(G),
+                          alpha, mom, effective_eta(g, p), p->min_gain, p->precision, true,
+                          reinterpret_cast<float2*>(grad_out), Z_out, s),
+            "launch update");
+  return TSGNE_OK;
+}
+
+tsgne_status kl_impl(tsgne_graph* g, const float* Y, double* kl_h, hipStream_t s) {
+  tsgne_status st = enqueue_forces(g, Y, TSGNE_PREC_SPLIT, s);
+  if (st != TSGNE_OK) return st;
+  {
+    Timed tm(g, TSGNE_PHASE_KL, s);
+    TSGNE_HIP(launch_kl(g, reinterpret_cast<const float2*>(Y), s), "launch KL");
+  }
+  TSGNE_HIP(hipMemcpyAsync(g->ws.pinned, g->ws.klout, sizeof(double), hipMemcpyDeviceToHost, s), "copy KL");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise KL");
+  *kl_h = g->ws.pinned[0];
+  return TSGNE_OK;
+}
+
+}  // namespace
+}  // namespace tsgne
+
+using namespace tsgne;
+
+extern "C" {
+
+void tsgne_params_default(tsgne_params* p) {
+  if (!p) return;
+  p->early_exaggeration = 12.0f;
+  p->exaggeration_iters = 250;
+  p->learning_rate = 0.0f;
+  p->momentum_early = 0.5f;
+  p->momentum_late = 0.8f;
+  p->min_gain = 0.01f;
+  p->precision = TSGNE_PREC_SPLIT;
+  p->kl_every = 0;
+  p->repulsion = TSGNE_REPULSION_AUTO;
+  p->tile_rows = 0;
+}
+
+const char* tsgne_last_error(void) { return g_error.c_str(); }
+
+const char* tsgne_status_string(tsgne_status s) {
+  switch (s) {
+    case TSGNE_OK: return "TSGNE_OK";
+    case TSGNE_E_INVAL: return "TSGNE_E_INVAL";
+    case TSGNE_E_GRAPH: return "TSGNE_E_GRAPH";
+    case TSGNE_E_NOMEM: return "TSGNE_E_NOMEM";
+    case TSGNE_E_DEVICE: return "TSGNE_E_DEVICE";
+    case TSGNE_E_NONFINITE: return "TSGNE_E_NONFINITE";
+    case TSGNE_E_BUSY: return "TSGNE_E_BUSY";
+    default: return "TSGNE_E_UNKNOWN";
+  }
+}
+
+// Counting sort by row, then per-row sort and de-duplication.
+tsgne_status tsgne_csr_from_edges(int32_t n, int64_t m, const int32_t* uv_h, int32_t* row_ptr_h, int32_t* col_h,
+                                  int64_t* nnz_out) {
+  if (n < 0 || m < 0) return fail(TSGNE_E_INVAL, "n and m must be >= 0");
+  if (!row_ptr_h || !nnz_out || (m > 0 && (!uv_h || !col_h))) return fail(TSGNE_E_INVAL, "null pointer");
+  std::vector<int64_t> count((size_t)n + 1, 0);
+  for (int64_t t = 0; t < m; ++t) {
+    const int32_t u = uv_h[2 * t], v = uv_h[2 * t + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n) return fail(TSGNE_E_INVAL, "edge endpoint outside [0, n)");
+    if (u == v) continue;
+    ++count[(size_t)u + 1];
+    ++count[(size_t)v + 1];
+  }
+  for (int32_t i = 0; i < n; ++i) count[(size_t)i + 1] += count[i];
+  if (count[n] >= ((int64_t)1 << 31)) return fail(TSGNE_E_INVAL, "graph has 2^31 or more stored entries");
+  std::vector<int64_t> fill(count.begin(), count.end() - 1);
+  std::vector<int32_t> tmp((size_t)count[n]);
+  for (int64_t t = 0; t < m; ++t) {
+    const int32_t u = uv_h[2 * t], v = uv_h[2 * t + 1];
+    if (u == v) continue;
+    tmp[(size_t)fill[u]++] = v;
+    tmp[(size_t)fill[v]++] = u;
+  }
+  int64_t w = 0;
+  row_ptr_h[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    auto first = tmp.begin() + count[i], last = tmp.begin() + count[(size_t)i + 1];
+    std::sort(first, last);
+    auto end = std::unique(first, last);
+    for (auto it = first; it != end; ++it) col_h[w++] = *it;
+    row_ptr_h[i + 1] = (int32_t)w;
+  }
+  *nnz_out = w;
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d, const float* X_d,
+                           int32_t d, float perplexity, void* stream, tsgne_graph** out) {
+  if (!out) return fail(TSGNE_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1) return fail(TSGNE_E_INVAL, "n must be >= 1");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return fail(TSGNE_E_INVAL, "nnz must lie in [0, 2^31)");
+  if (d < 1) return fail(TSGNE_E_INVAL, "d must be >= 1");
+  if (!std::isfinite(perplexity) || perplexity <= 1.0f) return fail(TSGNE_E_INVAL, "perplexity must be > 1");
+  if (!row_ptr_d || !X_d || (nnz > 0 && !col_d)) return fail(TSGNE_E_INVAL, "null pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  tsgne_graph* g = new (std::nothrow) tsgne_graph();
+  if (!g) return fail(TSGNE_E_NOMEM, "host allocation failed");
+  g->n = n;
+  g->nnz = nnz;
+  g->d = d;
+  g->perplexity = perplexity;
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return fail(TSGNE_E_DEVICE, "no HIP device");
+  }
+  struct Cleanup {
+    tsgne_graph* g;
+    ~Cleanup() { free_graph(g); }
+  } guard{g};
+
+  uint32_t* err = nullptr;
+  int32_t* counters = nullptr;
+  double* D = nullptr;
+  double* pcond = nullptr;
+  struct Scratch {
+    uint32_t*& err;
+    int32_t*& counters;
+    double*& D;
+    double*& pcond;
+    ~Scratch() {
+      dfree(err);
+      dfree(counters);
+      dfree(D);
+      dfree(pcond);
+    }
+  } scratch{err, counters, D, pcond};
+
+  const int32_t heavy_cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
+  TSGNE_HIP(dalloc(&g->row_ptr, (size_t)n + 1), "allocate row_ptr");
+  TSGNE_HIP(dalloc(&g->col, (size_t)nnz), "allocate col");
+  TSGNE_HIP(dalloc(&g->mirror, (size_t)nnz), "allocate mirror");
+  TSGNE_HIP(dalloc(&g->row_of, (size_t)nnz), "allocate row_of");
+  TSGNE_HIP(dalloc(&g->P, (size_t)nnz), "allocate P");
+  TSGNE_HIP(dalloc(&g->beta, (size_t)n), "allocate beta");
+  TSGNE_HIP(dalloc(&g->heavy, (size_t)heavy_cap), "allocate heavy rows");
+  TSGNE_HIP(dalloc(&err, 1), "allocate error word");
+  TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
+  TSGNE_HIP(dalloc(&D, (size_t)nnz), "allocate distances");
+  TSGNE_HIP(dalloc(&pcond, (size_t)nnz), "allocate conditional affinities");
+
+  TSGNE_HIP(hipMemcpyAsync(g->row_ptr, row_ptr_d, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s),
+            "copy row_ptr");
+  if (nnz > 0)
+    TSGNE_HIP(hipMemcpyAsync(g->col, col_d, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s), "copy col");
+  TSGNE_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s), "clear error word");
+  TSGNE_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s), "clear counters");
+
+  // 1. row_ptr must be valid before any kernel indexes col with it.
+  TSGNE_HIP(launch_check_rows(g->row_ptr, n, nnz, err, counters, g->heavy, s), "launch row check");
+  uint32_t host_err = 0;
+  int32_t host_counters[2] = {0, 0};
+  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
+  TSGNE_HIP(hipMemcpyAsync(host_counters, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "read counters");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise row check");
+  if (host_err) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
+  g->nonisolated = host_counters[0];
+  g->n_heavy = std::min(host_counters[1], heavy_cap);
+
+  // 2. Column checks, symmetry, mirror index.
+  TSGNE_HIP(launch_mirror(g->row_ptr, g->col, n, nnz, g->mirror, g->row_of, err, s), "launch mirror");
+  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise CSR check");
+  if (host_err) {
+    std::string why = "CSR is not canonical/symmetric:";
+    if (host_err & kErrColRange) why += " column outside [0, n);";
+    if (host_err & kErrSelfLoop) why += " self-loop;";
+    if (host_err & kErrOrder) why += " columns not strictly ascending;";
+    if (host_err & kErrAsym) why += " entry (i,j) without (j,i);";
+    return fail(TSGNE_E_GRAPH, why);
+  }
+
+  // 3. Distances, calibration, symmetrisation.
+  TSGNE_HIP(launch_sqdist(g->row_of, g->col, nnz, X_d, d, D, s), "launch distances");
+  TSGNE_HIP(launch_calibrate(g->row_ptr, n, g->heavy, g->n_heavy, D, (double)perplexity, pcond, g->beta, s),
+            "launch calibration");
+  const double S = 2.0 * (double)g->nonisolated;
+  TSGNE_HIP(launch_symmetrise(g->mirror, nnz, pcond, S, g->P, s), "launch symmetrisation");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise build_P");
+  guard.g = nullptr;
+  *out = g;
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_graph_free(tsgne_graph* g) {
+  free_graph(g);
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_graph_info(const tsgne_graph* g, int32_t* n, int64_t* nnz) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_graph_export(const tsgne_graph* g, int32_t* row_ptr_h, int32_t* col_h, int32_t* mirror_h,
+                                float* P_h, double* beta_h) {
+  if (tsgne_status st = check_graph(g)) return st;
+  DeviceGuard dg(g->device);
+  TSGNE_HIP(hipDeviceSynchronize(), "synchronise before export");
+  if (row_ptr_h)
+    TSGNE_HIP(hipMemcpy(row_ptr_h, g->row_ptr, sizeof(int32_t) * ((size_t)g->n + 1), hipMemcpyDeviceToHost),
+              "export row_ptr");
+  if (g->nnz > 0) {
+    if (col_h) TSGNE_HIP(hipMemcpy(col_h, g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost), "export col");
+    if (mirror_h)
+      TSGNE_HIP(hipMemcpy(mirror_h, g->mirror, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost), "export mirror");
+    if (P_h) TSGNE_HIP(hipMemcpy(P_h, g->P, sizeof(float) * g->nnz, hipMemcpyDeviceToHost), "export P");
+  }
+  if (beta_h) TSGNE_HIP(hipMemcpy(beta_h, g->beta, sizeof(double) * g->n, hipMemcpyDeviceToHost), "export beta");
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_gradient(tsgne_graph* g, const float* Y_d, float alpha, const tsgne_params* p, float* grad_d,
+                            double* Z_d, void* stream) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!Y_d || !grad_d) return fail(TSGNE_E_INVAL, "null pointer");
+  if (!std::isfinite(alpha)) return fail(TSGNE_E_INVAL, "alpha must be finite");
+  tsgne_params def;
+  tsgne_params_default(&def);
+  if (!p) p = &def;
+  if (tsgne_status st = validate_params(p)) return st;
+  DeviceGuard dg(g->device);
+  if (tsgne_status st = ensure_workspace(g, p)) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (tsgne_status st = enqueue_forces(g, Y_d, p->precision, s)) return st;
+  TSGNE_HIP(launch_update(g, nullptr, nullptr, nullptr, alpha, 0.f, 0.f, 0.f, p->precision, false,
+                          reinterpret_cast<float2*>(grad_d), Z_d, s),
+            "launch gradient");
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_step(tsgne_graph* g, float* Y_d, float* upd_d, float* gains_d, int32_t t, const tsgne_params* p,
+                        float* grad_out_d, double* Z_out_d, void* stream) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!Y_d || !upd_d || !gains_d || !p) return fail(TSGNE_E_INVAL, "null pointer");
+  if (t < 0) return fail(TSGNE_E_INVAL, "t must be >= 0");
+  if (tsgne_status st = validate_params(p)) return st;
+  DeviceGuard dg(g->device);
+  if (tsgne_status st = ensure_workspace(g, p)) return st;
+  return step_impl(g, Y_d, upd_d, gains_d, t, p, grad_out_d, Z_out_d, reinterpret_cast<hipStream_t>(stream));
+}
+
+tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, const tsgne_params* p, double* kl_trace_h,
+                       void* stream) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!Y_d || !p) return fail(TSGNE_E_INVAL, "null pointer");
+  if (n_iter < 0) return fail(TSGNE_E_INVAL, "n_iter must be >= 0");
+  if (tsgne_status st = validate_params(p)) return st;
+  DeviceGuard dg(g->device);
+  if (tsgne_status st = ensure_workspace(g, p)) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float *U = nullptr, *G = nullptr;
+  uint32_t* flag = nullptr;
+  struct Bufs {
+    float*& U;
+    float*& G;
+    uint32_t*& flag;
+    ~Bufs() {
+      dfree(U);
+      dfree(G);
+      dfree(flag);
+    }
+  } bufs{U, G, flag};
+  const size_t len = 2 * (size_t)g->n;
+  TSGNE_HIP(dalloc(&U, len), "allocate update buffer");
+  TSGNE_HIP(dalloc(&G, len), "allocate gains");
+  TSGNE_HIP(dalloc(&flag, 1), "allocate flag");
+  {
+    std::vector<float> ones(len, 1.0f);
+    TSGNE_HIP(hipMemsetAsync(U, 0, len * sizeof(float), s), "clear update buffer");
+    TSGNE_HIP(hipMemcpyAsync(G, ones.data(), len * sizeof(float), hipMemcpyHostToDevice, s), "set gains");
+    TSGNE_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s), "clear flag");
+    TSGNE_HIP(hipStreamSynchronize(s), "synchronise run set-up");
+  }
+  int32_t k = 0;
+  for (int32_t t = 0; t < n_iter; ++t) {
+    if (tsgne_status st = step_impl(g, Y_d, U, G, t, p, nullptr, nullptr, s)) return st;
+    if (kl_trace_h && p->kl_every > 0 && (t + 1) % p->kl_every == 0) {
+      double kl = 0.0;
+      if (tsgne_status st = kl_impl(g, Y_d, &kl, s)) return st;
+      kl_trace_h[k++] = kl;
+    }
+  }
+  TSGNE_HIP(launch_nonfinite_check(reinterpret_cast<const float2*>(Y_d), g->n, flag, s), "launch finiteness check");
+  uint32_t host_flag = 0;
+  TSGNE_HIP(hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read flag");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise run");
+  if (host_flag) return fail(TSGNE_E_NONFINITE, "layout holds a NaN or infinity");
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, void* stream) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!Y_d || !kl_h) return fail(TSGNE_E_INVAL, "null pointer");
+  tsgne_params def;
+  tsgne_params_default(&def);
+  DeviceGuard dg(g->device);
+  if (!g->ws.part)
+    if (tsgne_status st = ensure_workspace(g, &def)) return st;
+  return kl_impl(g, Y_d, kl_h, reinterpret_cast<hipStream_t>(stream));
+}
+
+tsgne_status tsgne_graph_set_timing(tsgne_graph* g, int32_t enable) {
+  if (tsgne_status st = check_graph(g)) return st;
+  DeviceGuard dg(g->device);
+  TSGNE_HIP(timer_resolve(g), "resolve timing events");
+  PhaseTimer& t = g->timer;
+  t.enabled = enable != 0;
+  for (int k = 0; k < TSGNE_NUM_PHASES; ++k) {
+    t.ms[k] = 0.0;
+    t.launches[k] = 0;
+  }
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_graph_timing(tsgne_graph* g, tsgne_timing* out) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!out) return fail(TSGNE_E_INVAL, "out is NULL");
+  DeviceGuard dg(g->device);
+  TSGNE_HIP(timer_resolve(g), "resolve timing events");
+  for (int k = 0; k < TSGNE_NUM_PHASES; ++k) {
+    out->ms[k] = g->timer.ms[k];
+    out->launches[k] = g->timer.launches[k];
+  }
+  return TSGNE_OK;
+}
+
+}  // extern "C"

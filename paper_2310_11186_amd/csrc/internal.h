@@ -1,0 +1,117 @@
+// Internal declarations of the t-SGNE HIP library: the graph handle, the
+// repulsion tiling plan and the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tsgne.h"
+
+namespace tsgne {
+
+// Rows per wave lane in the repulsion tile: a tile spans 64 * R positions.
+constexpr int kWave = 64;
+
+// Degree above which a row is handled by a whole wave (calibration, attraction).
+constexpr int32_t kHeavyDegree = 64;
+
+// Bits of the device error word written by the CSR check.
+enum : uint32_t {
+  kErrRowPtr = 1u << 0,   // row_ptr not monotone or not spanning [0, nnz]
+  kErrColRange = 1u << 1, // column outside [0, n)
+  kErrSelfLoop = 1u << 2,
+  kErrOrder = 1u << 3,    // columns not strictly ascending in a row
+  kErrAsym = 1u << 4,     // (i, j) stored without (j, i)
+};
+
+// All-pairs repulsion plan: positions are cut into nb blocks of T = 64 * R;
+// tile (a, b) covers rows of block a against columns of block b.
+struct RepulsionPlan {
+  int32_t R = 0;        // rows per lane
+  int32_t T = 0;        // block length = 64 * R
+  int32_t nb = 0;       // number of blocks, the last one possibly partial
+  int32_t variant = 0;  // TSGNE_REPULSION_DIRECT or _SYMMETRIC
+  int64_t items = 0;    // work items (one wave each)
+};
+
+struct Workspace {
+  RepulsionPlan plan;
+  int2* items = nullptr;        // (a, b) per work item
+  float2* part = nullptr;       // [nb][nb][T] force partials: part[k][o] = sum over block o acting on block k
+  double* zpart = nullptr;      // [items] Z partial of each item (ordered pairs)
+  double* Z = nullptr;          // [1] normaliser
+  float* zpart32 = nullptr;     // [items] FP32-mode partials
+  double2* attract = nullptr;   // [n] sum_j P_ij w_ij (y_i - y_j) (unscaled by alpha)
+  double* klpart = nullptr;     // [kl_blocks] KL partial sums
+  double* klout = nullptr;      // [1]
+  double* pinned = nullptr;     // host-pinned scratch for read-backs
+  int32_t kl_blocks = 0;
+};
+
+// Event-pair timing of kernel phases (see tsgne_graph_set_timing).
+struct PhaseTimer {
+  struct Pending {
+    int phase;
+    hipEvent_t start, stop;
+  };
+  bool enabled = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[TSGNE_NUM_PHASES] = {};
+  int64_t launches[TSGNE_NUM_PHASES] = {};
+};
+
+}  // namespace tsgne
+
+struct tsgne_graph {
+  int device = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int32_t d = 0;
+  float perplexity = 0.f;
+  int32_t* row_ptr = nullptr;   // [n+1]
+  int32_t* col = nullptr;       // [nnz]
+  int32_t* mirror = nullptr;    // [nnz]
+  int32_t* row_of = nullptr;    // [nnz] row of each entry
+  float* P = nullptr;           // [nnz]
+  double* beta = nullptr;       // [n]
+  int32_t* heavy = nullptr;     // rows with degree > kHeavyDegree
+  int32_t n_heavy = 0;
+  int64_t nonisolated = 0;
+  tsgne::Workspace ws;
+  tsgne::PhaseTimer timer;
+};
+
+namespace tsgne {
+
+// Thread-local error message.
+void set_error(const std::string& msg);
+
+// Launchers (return hipSuccess or the first HIP error).
+hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, uint32_t* err, int32_t* counters,
+                             int32_t* heavy, hipStream_t s);
+hipError_t launch_mirror(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz, int32_t* mirror,
+                         int32_t* row_of, uint32_t* err, hipStream_t s);
+hipError_t launch_sqdist(const int32_t* row_of, const int32_t* col, int64_t nnz, const float* X, int32_t d,
+                         double* D, hipStream_t s);
+hipError_t launch_calibrate(const int32_t* row_ptr, int32_t n, const int32_t* heavy, int32_t n_heavy, const double* D,
+                            double perplexity, double* pcond, double* beta, hipStream_t s);
+hipError_t launch_symmetrise(const int32_t* mirror, int64_t nnz, const double* pcond, double S, float* P,
+                             hipStream_t s);
+
+hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s);
+hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s);
+hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, hipStream_t s);
+hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gains, float alpha, float momentum,
+                         float eta, float min_gain, int precision, bool do_update, float2* grad_out, double* Z_out,
+                         hipStream_t s);
+hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s);
+hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s);
+
+// Repulsion plan for n positions (R = 0 picks automatically).
+RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant);
+
+}  // namespace tsgne

@@ -1,0 +1,603 @@
+// Per-step kernels of the t-SGNE loop: all-pairs Student-t repulsion with its
+// normaliser Z (eq. (4)), the sparse attraction over graph edges, the gradient
+// of eq. (5) and the momentum/gains update, and KL(P || Q).
+//
+// Repulsion tiling.  Positions are cut into nb blocks of T = 64 * R.  A work
+// item is one tile (a, b) processed by one wave; each lane keeps R "resident"
+// rows of block a in registers.
+//  - Symmetric tiles (a < b): the 64-position sub-blocks of b travel around the
+//    wave (a DPP rotation by one lane per step), so every unordered pair
+//    (i, j) is met exactly once; w_ij is computed once and its force is added
+//    to the resident row (+) and to the travelling column (-).  After 64 steps
+//    each travelling position is back in its own lane with its column sum.
+//  - Direct tiles (every tile of the direct variant): columns of b are read as
+//    wave-uniform values and each ordered pair is computed by the row's lane;
+//    the i == j term is masked by index.  Diagonal tiles of the symmetric
+//    variant use the same scheme one resident row at a time.
+// Each tile writes its row sums to part[a][b] and (symmetric) its column sums
+// to part[b][a], so part[k][*] holds every contribution to block k exactly
+// once and the update kernel adds them in a fixed order: results do not
+// depend on scheduling.  Z partials are per tile.
+#include <cmath>
+
+#include "internal.h"
+
+namespace tsgne {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__device__ __forceinline__ float rotate_lanes(float v) {
+  // wave_ror:1 -- every lane takes the value of its neighbour, 64-lane ring.
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// w = 1 / (1 + dx^2 + dy^2) with the hardware reciprocal (q >= 1, <= 1 ulp).
+__device__ __forceinline__ float student_w(float dx, float dy) {
+  return __builtin_amdgcn_rcpf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f)));
+}
+
+// Symmetric tile (a < b).  Block a is always full (a < nb - 1).
+// Accumulation is two-level to keep FP32 chains short: the travelling sum of
+// one step (R terms) is formed apart and then added, and the resident sums are
+// folded into a second FP32 sum after every 64-step pass.
+template <int R, bool SPLIT, bool MASKED>
+__device__ __forceinline__ void sym_pass(const float (&yix)[R], const float (&yiy)[R], float (&rix)[R],
+                                         float (&riy)[R], float& tx, float& ty, float& fx, float& fy, float& m,
+                                         double& z64, float& z32) {
+#pragma unroll 2
+  for (int s = 0; s < kWave; ++s) {
+    float zs = 0.f, sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float dx = yix[r] - tx, dy = yiy[r] - ty;
+      float w = student_w(dx, dy);
+      if (MASKED) w *= m;
+      zs += w;
+      const float w2 = w * w;
+      rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+      riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+      sx = __builtin_fmaf(w2, dx, sx);
+      sy = __builtin_fmaf(w2, dy, sy);
+    }
+    fx -= sx;
+    fy -= sy;
+    if (SPLIT) z64 += (double)zs; else z32 += zs;
+    tx = rotate_lanes(tx);
+    ty = rotate_lanes(ty);
+    fx = rotate_lanes(fx);
+    fy = rotate_lanes(fy);
+    if (MASKED) m = rotate_lanes(m);
+  }
+}
+
+template <int R, bool SPLIT>
+__device__ void tile_symmetric(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+                               float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
+                               int64_t item, int lane) {
+  constexpr int T = kWave * R;
+  const int32_t valid_b = min(T, n - b * T);
+  float yix[R], yiy[R], rix[R], riy[R], hix[R], hiy[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float2 v = Y[(int64_t)a * T + r * kWave + lane];
+    yix[r] = v.x;
+    yiy[r] = v.y;
+    rix[r] = riy[r] = hix[r] = hiy[r] = 0.f;
+  }
+  double z64 = 0.0;
+  float z32 = 0.f;
+  for (int q = 0; q < R; ++q) {
+    if (q * kWave >= valid_b) break;  // wave-uniform
+    const int jl = q * kWave + lane;
+    const bool vj = jl < valid_b;
+    const float2 v = vj ? Y[(int64_t)b * T + jl] : make_float2(0.f, 0.f);
+    float tx = v.x, ty = v.y, fx = 0.f, fy = 0.f;
+    // partially valid sub-block (last block only): the mask travels with its position
+    float m = vj ? 1.f : 0.f;
+    if (q * kWave + kWave <= valid_b)
+      sym_pass<R, SPLIT, false>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
+    else
+      sym_pass<R, SPLIT, true>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      hix[r] += rix[r];
+      hiy[r] += riy[r];
+      rix[r] = riy[r] = 0.f;
+    }
+    if (vj) part[((int64_t)b * nb + a) * T + jl] = make_float2(fx, fy);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+  // every unordered pair stands for the two ordered pairs of Z
+  if (SPLIT) {
+    const double z = wave_sum(z64);
+    if (lane == 0) zpart[item] = 2.0 * z;
+  } else {
+    const float z = wave_sum(z32);
+    if (lane == 0) zpart32[item] = 2.0f * z;
+  }
+}
+
+// Direct tile: rows of block a against every valid column of block b.
+// SELF (a == b) masks the i == j term by index; MASK_I masks rows past n
+// (only the last block is partial).  Full off-diagonal tiles run unmasked.
+template <int R, bool SPLIT, bool SELF, bool MASK_I>
+__device__ void tile_direct_body(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+                                 float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
+                                 int64_t item, int lane) {
+  constexpr int T = kWave * R;
+  const int32_t valid_a = min(T, n - a * T);
+  const int32_t valid_b = min(T, n - b * T);
+  float yix[R], yiy[R], rix[R], riy[R], hix[R], hiy[R];
+  bool vi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int il = r * kWave + lane;
+    vi[r] = !MASK_I || il < valid_a;
+    const float2 v = vi[r] ? Y[(int64_t)a * T + il] : make_float2(0.f, 0.f);
+    yix[r] = v.x;
+    yiy[r] = v.y;
+    rix[r] = riy[r] = hix[r] = hiy[r] = 0.f;
+  }
+  const float2* __restrict__ Yb = Y + (int64_t)b * T;
+  double z64 = 0.0;
+  float z32 = 0.f;
+  // columns in chunks of 64, each chunk's row sums folded into a second sum
+  for (int j0 = 0; j0 < valid_b; j0 += kWave) {
+    const int j1 = min(j0 + kWave, valid_b);
+    for (int jl = j0; jl < j1; ++jl) {
+      const float2 v = Yb[jl];
+      float zs = 0.f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float dx = yix[r] - v.x, dy = yiy[r] - v.y;
+        float w = student_w(dx, dy);
+        if (SELF || MASK_I) {
+          const bool keep = vi[r] && !(SELF && jl == r * kWave + lane);
+          w = keep ? w : 0.f;
+        }
+        zs += w;
+        const float w2 = w * w;
+        rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+        riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+      }
+      if (SPLIT) z64 += (double)zs; else z32 += zs;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      hix[r] += rix[r];
+      hiy[r] += riy[r];
+      rix[r] = riy[r] = 0.f;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (vi[r]) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+  if (SPLIT) {
+    const double z = wave_sum(z64);
+    if (lane == 0) zpart[item] = z;
+  } else {
+    const float z = wave_sum(z32);
+    if (lane == 0) zpart32[item] = z;
+  }
+}
+
+template <int R, bool SPLIT>
+__device__ void tile_direct(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+                            float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
+                            int64_t item, int lane) {
+  const bool partial_a = (int64_t)(a + 1) * (kWave * R) > n;
+  if (a == b) {
+    if (partial_a) tile_direct_body<R, SPLIT, true, true>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    else tile_direct_body<R, SPLIT, true, false>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+  } else {
+    if (partial_a) tile_direct_body<R, SPLIT, false, true>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    else tile_direct_body<R, SPLIT, false, false>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+  }
+}
+
+// Diagonal tile (a, a) inside the symmetric kernel: one resident row per lane
+// per pass (few registers, so the symmetric path keeps its occupancy), every
+// ordered pair i != j, four interleaved partial sums per coordinate.
+template <int R, bool SPLIT>
+__device__ void tile_diag_light(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a,
+                                float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
+                                int64_t item, int lane) {
+  constexpr int T = kWave * R;
+  const int32_t valid = min(T, n - a * T);
+  const float2* __restrict__ Ya = Y + (int64_t)a * T;
+  double z64 = 0.0;
+  float z32 = 0.f;
+  for (int r = 0; r < R; ++r) {
+    const int il = r * kWave + lane;
+    if (r * kWave >= valid) break;  // wave-uniform
+    const bool vi = il < valid;
+    const float2 yi = vi ? Ya[il] : make_float2(0.f, 0.f);
+    float hx = 0.f, hy = 0.f;
+    for (int j0 = 0; j0 < valid; j0 += kWave) {
+      const int j1 = min(j0 + kWave, valid);
+      float ax[4] = {0.f, 0.f, 0.f, 0.f}, ay[4] = {0.f, 0.f, 0.f, 0.f}, az[4] = {0.f, 0.f, 0.f, 0.f};
+      int jl = j0;
+      for (; jl + 4 <= j1; jl += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float2 v = Ya[jl + k];
+          const float dx = yi.x - v.x, dy = yi.y - v.y;
+          float w = student_w(dx, dy);
+          w = (vi && jl + k != il) ? w : 0.f;
+          az[k] += w;
+          const float w2 = w * w;
+          ax[k] = __builtin_fmaf(w2, dx, ax[k]);
+          ay[k] = __builtin_fmaf(w2, dy, ay[k]);
+        }
+      }
+      for (; jl < j1; ++jl) {
+        const float2 v = Ya[jl];
+        const float dx = yi.x - v.x, dy = yi.y - v.y;
+        float w = student_w(dx, dy);
+        w = (vi && jl != il) ? w : 0.f;
+        az[0] += w;
+        const float w2 = w * w;
+        ax[0] = __builtin_fmaf(w2, dx, ax[0]);
+        ay[0] = __builtin_fmaf(w2, dy, ay[0]);
+      }
+      hx += (ax[0] + ax[1]) + (ax[2] + ax[3]);
+      hy += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+      const float zc = (az[0] + az[1]) + (az[2] + az[3]);
+      if (SPLIT) z64 += (double)zc; else z32 += zc;
+    }
+    if (vi) part[((int64_t)a * nb + a) * T + il] = make_float2(hx, hy);
+  }
+  if (SPLIT) {
+    const double z = wave_sum(z64);
+    if (lane == 0) zpart[item] = z;
+  } else {
+    const float z = wave_sum(z32);
+    if (lane == 0) zpart32[item] = z;
+  }
+}
+
+template <int R, bool SPLIT, bool SYM>
+__global__ __launch_bounds__(kBlock) void k_repulse(const float2* __restrict__ Y, int32_t n, int32_t nb,
+                                                    const int2* __restrict__ items, int64_t n_items,
+                                                    float2* __restrict__ part, double* __restrict__ zpart,
+                                                    float* __restrict__ zpart32) {
+  const int64_t item =
+      (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int2 ab = items[item];
+  const int32_t a = __builtin_amdgcn_readfirstlane(ab.x), b = __builtin_amdgcn_readfirstlane(ab.y);
+  if (SYM) {
+    if (a != b) tile_symmetric<R, SPLIT>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    else tile_diag_light<R, SPLIT>(Y, n, nb, a, part, zpart, zpart32, item, lane);
+  } else {
+    tile_direct<R, SPLIT>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+  }
+}
+
+template <int R>
+hipError_t launch_repulsion_r(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s) {
+  const RepulsionPlan& p = ws.plan;
+  const dim3 grid((unsigned)((p.items + kWavesPerBlock - 1) / kWavesPerBlock));
+  const bool split = precision != TSGNE_PREC_FP32;
+  const bool sym = p.variant == TSGNE_REPULSION_SYMMETRIC;
+  if (split && sym)
+    hipLaunchKernelGGL((k_repulse<R, true, true>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.part,
+                       ws.zpart, ws.zpart32);
+  else if (split)
+    hipLaunchKernelGGL((k_repulse<R, true, false>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.part,
+                       ws.zpart, ws.zpart32);
+  else if (sym)
+    hipLaunchKernelGGL((k_repulse<R, false, true>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.part,
+                       ws.zpart, ws.zpart32);
+  else
+    hipLaunchKernelGGL((k_repulse<R, false, false>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items,
+                       ws.part, ws.zpart, ws.zpart32);
+  return hipGetLastError();
+}
+
+// Z = sum of the tile partials, one workgroup, fixed order (strided partial
+// sums then a tree in LDS).
+constexpr int kZThreads = 1024;
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ zpart, const float* __restrict__ zpart32,
+                                                    int64_t n_items, double* __restrict__ Z) {
+  __shared__ double sh64[kZThreads];
+  __shared__ float sh32[kZThreads];
+  const int t = threadIdx.x;
+  if (SPLIT) {
+    double acc = 0.0;
+    for (int64_t k = t; k < n_items; k += kZThreads) acc += zpart[k];
+    sh64[t] = acc;
+  } else {
+    float acc = 0.f;
+    for (int64_t k = t; k < n_items; k += kZThreads) acc += zpart32[k];
+    sh32[t] = acc;
+  }
+  __syncthreads();
+  for (int w = kZThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      if (SPLIT) sh64[t] += sh64[t + w]; else sh32[t] += sh32[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) *Z = SPLIT ? sh64[0] : (double)sh32[0];
+}
+
+// Attraction sum_j p_ij w_ij (y_i - y_j) over the stored entries of row i
+// (the p-part of the gradient of eq. (5); alpha is applied in the update).
+// Light rows: eight lanes per row.  Heavy rows: one wave per row.
+constexpr int kRowLanes = 8;
+
+template <int LANES, bool SPLIT>
+__device__ void attract_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const float* __restrict__ P, const float2* __restrict__ Y, int32_t i, int sub,
+                            double2* __restrict__ out) {
+  const int32_t b = row_ptr[i], e_end = row_ptr[i + 1];
+  const float2 yi = Y[i];
+  double ax = 0.0, ay = 0.0;
+  float fx = 0.f, fy = 0.f;
+  for (int32_t e = b + sub; e < e_end; e += LANES) {
+    const float2 yj = Y[col[e]];
+    const float dx = yi.x - yj.x, dy = yi.y - yj.y;
+    const float pw = P[e] * student_w(dx, dy);
+    if (SPLIT) {
+      ax += (double)(pw * dx);
+      ay += (double)(pw * dy);
+    } else {
+      fx = __builtin_fmaf(pw, dx, fx);
+      fy = __builtin_fmaf(pw, dy, fy);
+    }
+  }
+  if (!SPLIT) {
+    ax = fx;
+    ay = fy;
+  }
+  for (int off = LANES / 2; off > 0; off >>= 1) {
+    if (SPLIT) {
+      ax += __shfl_xor(ax, off, LANES);
+      ay += __shfl_xor(ay, off, LANES);
+    } else {
+      fx += __shfl_xor(fx, off, LANES);
+      fy += __shfl_xor(fy, off, LANES);
+    }
+  }
+  if (!SPLIT) {
+    ax = fx;
+    ay = fy;
+  }
+  if (sub == 0) out[i] = make_double2(ax, ay);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_attract_light(const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col, const float* __restrict__ P,
+                                                          const float2* __restrict__ Y, int32_t n,
+                                                          double2* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int32_t i = (int32_t)min<int64_t>(t / kRowLanes, n - 1);
+  const bool live = t / kRowLanes < n && (row_ptr[i + 1] - row_ptr[i]) <= kHeavyDegree;
+  // whole 8-lane groups share `live`, so the shuffles inside stay in step
+  if (live) attract_row<kRowLanes, SPLIT>(row_ptr, col, P, Y, i, (int)(threadIdx.x & (kRowLanes - 1)), out);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_attract_heavy(const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col, const float* __restrict__ P,
+                                                          const float2* __restrict__ Y,
+                                                          const int32_t* __restrict__ heavy, int32_t n_heavy,
+                                                          double2* __restrict__ out) {
+  const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
+  if (w >= n_heavy) return;
+  attract_row<kWave, SPLIT>(row_ptr, col, P, Y, heavy[w], (int)(threadIdx.x & (kWave - 1)), out);
+}
+
+// g_i = 4 (alpha * A_i - R_i / Z), then the momentum/gains update.
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ part, int32_t nb, int32_t T,
+                                                   const double2* __restrict__ attract, const double* __restrict__ Zp,
+                                                   int32_t n, float2* __restrict__ Y, float2* __restrict__ U,
+                                                   float2* __restrict__ G, float alpha, float momentum, float eta,
+                                                   float min_gain, int do_update, float2* __restrict__ grad_out) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k = i / T, off = i - k * T;
+  const float2* __restrict__ pp = part + (int64_t)k * nb * T + off;
+  double rx = 0.0, ry = 0.0;
+  float sx = 0.f, sy = 0.f;
+  for (int32_t o = 0; o < nb; ++o) {
+    const float2 v = pp[(int64_t)o * T];
+    if (SPLIT) {
+      rx += v.x;
+      ry += v.y;
+    } else {
+      sx += v.x;
+      sy += v.y;
+    }
+  }
+  const double Z = *Zp;
+  const double2 A = attract[i];
+  float2 g;
+  if (SPLIT) {
+    const double invZ = Z > 0.0 ? 1.0 / Z : 0.0;
+    g.x = (float)(4.0 * ((double)alpha * A.x - rx * invZ));
+    g.y = (float)(4.0 * ((double)alpha * A.y - ry * invZ));
+  } else {
+    const float invZ = Z > 0.0 ? (float)(1.0 / Z) : 0.f;
+    g.x = 4.0f * (alpha * (float)A.x - sx * invZ);
+    g.y = 4.0f * (alpha * (float)A.y - sy * invZ);
+  }
+  if (grad_out) grad_out[i] = g;
+  if (!do_update) return;
+  float2 y = Y[i], u = U[i], gn = G[i];
+  gn.x = (g.x * u.x < 0.f) ? gn.x + 0.2f : gn.x * 0.8f;
+  gn.y = (g.y * u.y < 0.f) ? gn.y + 0.2f : gn.y * 0.8f;
+  gn.x = fmaxf(gn.x, min_gain);
+  gn.y = fmaxf(gn.y, min_gain);
+  u.x = momentum * u.x - eta * gn.x * g.x;
+  u.y = momentum * u.y - eta * gn.y * g.y;
+  y.x += u.x;
+  y.y += u.y;
+  Y[i] = y;
+  U[i] = u;
+  G[i] = gn;
+}
+
+// KL = sum_e P_e log(P_e / q_e), q_e = w_e / Z, in FP64: fixed grid, strided
+// per-thread sums, tree per block, then one block over the block sums.
+constexpr int kKLThreads = 256;
+
+__global__ __launch_bounds__(kKLThreads) void k_kl_edges(const int32_t* __restrict__ row_of,
+                                                         const int32_t* __restrict__ col, const float* __restrict__ P,
+                                                         const float2* __restrict__ Y, int64_t nnz,
+                                                         const double* __restrict__ Zp, double* __restrict__ klpart) {
+  __shared__ double sh[kKLThreads];
+  const double logZ = *Zp > 0.0 ? log(*Zp) : 0.0;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kKLThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kKLThreads + threadIdx.x; e < nnz; e += stride) {
+    const double p = P[e];
+    if (p <= 0.0) continue;
+    const float2 yi = Y[row_of[e]], yj = Y[col[e]];
+    const double dx = (double)yi.x - (double)yj.x, dy = (double)yi.y - (double)yj.y;
+    acc += p * (log(p) + logZ + log1p(dx * dx + dy * dy));
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kKLThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) klpart[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kKLThreads) void k_kl_final(const double* __restrict__ klpart, int32_t nparts,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[kKLThreads];
+  double acc = 0.0;
+  for (int32_t k = threadIdx.x; k < nparts; k += kKLThreads) acc += klpart[k];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kKLThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_nonfinite(const float2* __restrict__ Y, int32_t n,
+                                                      uint32_t* __restrict__ flag) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float2 y = Y[i];
+  if (!isfinite(y.x) || !isfinite(y.y)) atomicOr(flag, 1u);
+}
+
+inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + per - 1) / per); }
+
+}  // namespace
+
+RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
+  RepulsionPlan p;
+  p.variant = (variant == TSGNE_REPULSION_DIRECT) ? TSGNE_REPULSION_DIRECT : TSGNE_REPULSION_SYMMETRIC;
+  auto items_for = [&](int32_t r) {
+    const int64_t nb = (n + kWave * r - 1) / (kWave * r);
+    return p.variant == TSGNE_REPULSION_DIRECT ? nb * nb : nb * (nb + 1) / 2;
+  };
+  if (R != 4 && R != 8 && R != 16) {
+    // Largest tile that still leaves ~8 waves of work per SIMD (1024 SIMDs).
+    R = 4;
+    if (items_for(16) >= 8192) R = 16;
+    else if (items_for(8) >= 8192) R = 8;
+  }
+  p.R = R;
+  p.T = kWave * R;
+  p.nb = (n + p.T - 1) / p.T;
+  p.items = items_for(R);
+  return p;
+}
+
+hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s) {
+  switch (ws.plan.R) {
+    case 4: return launch_repulsion_r<4>(ws, n, Y, precision, s);
+    case 8: return launch_repulsion_r<8>(ws, n, Y, precision, s);
+    case 16: return launch_repulsion_r<16>(ws, n, Y, precision, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s) {
+  if (precision == TSGNE_PREC_FP32)
+    hipLaunchKernelGGL(k_zsum<false>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z);
+  else
+    hipLaunchKernelGGL(k_zsum<true>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, hipStream_t s) {
+  const bool split = precision != TSGNE_PREC_FP32;
+  const unsigned lb = blocks_for((int64_t)g->n * kRowLanes, kBlock);
+  if (split)
+    hipLaunchKernelGGL(k_attract_light<true>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n,
+                       g->ws.attract);
+  else
+    hipLaunchKernelGGL(k_attract_light<false>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n,
+                       g->ws.attract);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g->n_heavy == 0) return e;
+  const unsigned hb = blocks_for(g->n_heavy, kWavesPerBlock);
+  if (split)
+    hipLaunchKernelGGL(k_attract_heavy<true>, dim3(hb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->heavy,
+                       g->n_heavy, g->ws.attract);
+  else
+    hipLaunchKernelGGL(k_attract_heavy<false>, dim3(hb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->heavy,
+                       g->n_heavy, g->ws.attract);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gains, float alpha, float momentum,
+                         float eta, float min_gain, int precision, bool do_update, float2* grad_out, double* Z_out,
+                         hipStream_t s) {
+  const Workspace& ws = g->ws;
+  const unsigned nbk = blocks_for(g->n, kBlock);
+  if (precision == TSGNE_PREC_FP32)
+    hipLaunchKernelGGL(k_update<false>, dim3(nbk), dim3(kBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, ws.attract,
+                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out);
+  else
+    hipLaunchKernelGGL(k_update<true>, dim3(nbk), dim3(kBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, ws.attract,
+                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !Z_out) return e;
+  return hipMemcpyAsync(Z_out, ws.Z, sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s) {
+  const Workspace& ws = g->ws;
+  hipLaunchKernelGGL(k_kl_edges, dim3(ws.kl_blocks), dim3(kKLThreads), 0, s, g->row_of, g->col, g->P, Y, g->nnz, ws.Z,
+                     ws.klpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kKLThreads), 0, s, ws.klpart, ws.kl_blocks, ws.klout);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, Y, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace tsgne

