@@ -25,7 +25,7 @@ _lib = None
 
 __all__ = [
     "build", "lib", "num_threads", "set_threads", "csr_from_edges", "mirror", "edge_sqdist", "calibrate",
-    "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "update", "run", "OracleError",
+    "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
 
@@ -64,6 +64,7 @@ def lib():
             "oracle_gradient": (None, [i32, vp, vp, vp, vp, dbl, vp, vp]),
             "oracle_gradient_rows": (None, [i32, vp, vp, vp, vp, dbl, vp, i32, vp, vp]),
             "oracle_kl": (dbl, [i32, vp, vp, vp, vp]),
+            "oracle_kl_given_Z": (dbl, [i32, vp, vp, vp, vp, dbl]),
             "oracle_update": (None, [i32, vp, vp, vp, vp, dbl, dbl, dbl]),
             "oracle_run": (None, [i32, vp, vp, vp, vp, vp, vp, i32, i32, dbl, i32, dbl, dbl, dbl, dbl, i32, vp]),
         }
@@ -194,6 +195,12 @@ def gradient_rows(row_ptr, col, P, Y, rows, alpha: float = 1.0) -> tuple[np.ndar
 def kl(row_ptr, col, P, Y) -> float:
     row_ptr, col, P, Y = _i32(row_ptr), _i32(col), _f64(P), _f64(Y)
     return float(lib().oracle_kl(Y.shape[0], _p(row_ptr), _p(col), _p(P), _p(Y)))
+
+
+def kl_given_Z(row_ptr, col, P, Y, Z: float) -> float:
+    """KL at Y with Q's normaliser Z supplied (from Z() or gradient*() at the same Y)."""
+    row_ptr, col, P, Y = _i32(row_ptr), _i32(col), _f64(P), _f64(Y)
+    return float(lib().oracle_kl_given_Z(Y.shape[0], _p(row_ptr), _p(col), _p(P), _p(Y), float(Z)))
 
 
 def update(Y, U, gains, g, momentum: float, eta: float, min_gain: float = 0.01):

@@ -215,7 +215,7 @@ void oracle_calibrate(int32_t n, const int32_t* row_ptr, const double* D, double
       beta[i] = INFINITY;
       continue;
     }
-    double* delta = (double*)malloc(sizeof(double) * (size_t)deg);
+    double* delta = (double*)malloc(sizeof(double) * (size_t)(deg > 0 ? deg : 1));
     double mean = 0.0;
     for (int64_t k = 0; k < deg; ++k) {
       delta[k] = D[b + k] - dmin;
@@ -360,9 +360,10 @@ void oracle_gradient(int32_t n, const int32_t* row_ptr, const int32_t* col, cons
   oracle_gradient_rows(n, row_ptr, col, P, Y, alpha, NULL, n, g, Z_out);
 }
 
-/* KL(P || Q) of eq. (5) with q_ij = w_ij / Z; terms with p_ij = 0 vanish. */
-double oracle_kl(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y) {
-  double Z = oracle_Z(n, Y);
+/* KL(P || Q) of eq. (5) with q_ij = w_ij / Z for a given Z (the all-pairs
+ * sum of oracle_Z at the same Y); terms with p_ij = 0 vanish. */
+double oracle_kl_given_Z(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y,
+                         double Z) {
   double kl = 0.0;
   for (int32_t i = 0; i < n; ++i) {
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -372,6 +373,11 @@ double oracle_kl(int32_t n, const int32_t* row_ptr, const int32_t* col, const do
     }
   }
   return kl;
+}
+
+/* KL(P || Q) of eq. (5) at Y. */
+double oracle_kl(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y) {
+  return oracle_kl_given_Z(n, row_ptr, col, P, Y, oracle_Z(n, Y));
 }
 
 /* ------------------------------------------------------------------ */

@@ -29,8 +29,11 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 __device__ __forceinline__ float rotate_lanes(float v) {
-  // wave_ror:1 -- every lane takes the value of its neighbour, 64-lane ring.
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
+  // wave_ror:1 -- every lane takes the value of its neighbour on a 64-lane
+  // ring.  Every source lane exists, so the "old" operand is never used; passing
+  // the value itself lets the move happen in place.
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x13C, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
