@@ -190,6 +190,39 @@ TSGNE_API tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, con
 TSGNE_API tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, void* stream);
 
 /*
+ * Advances many independent graphs together (the same optimiser as
+ * tsgne_run, eqs. (4)-(5) per graph).  graphs[k] / Y_d[k] (float32[n_k][2], in:
+ * Y0, out: final layout) for k < count; graph k takes n_iter[k] steps
+ * t = 0 .. n_iter[k]-1 with the schedule of p (early exaggeration and
+ * momentum switch at p->exaggeration_iters).  Each step is one set of fused
+ * launches for the whole batch (repulsion tiles of every graph, per-graph Z,
+ * attraction, update), captured once as a HIP graph and replayed.  All graphs
+ * use the repulsion tile p->tile_rows (4, 8, 16; 0 = chosen from the batch's
+ * total tile count) with symmetric tiles; each graph's arithmetic and
+ * reduction order are its own, so its result equals tsgne_run of that graph
+ * alone with the same tile_rows and the symmetric repulsion, bit for bit.
+ * Graphs must be distinct and on one device; layouts must not alias.  The
+ * graphs' step workspaces are re-planned for the batch tile.  stream may be
+ * NULL (a private stream is used).  Synchronising.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE (a final layout holds a NaN
+ * or infinity).
+ */
+TSGNE_API tsgne_status tsgne_batch_run(tsgne_graph* const* graphs, float* const* Y_d, const int32_t* n_iter,
+                                       int32_t count, const tsgne_params* p, void* stream);
+
+/*
+ * Autotuner: times `steps` batched steps (after one warm-up step) of the given
+ * graphs for each repulsion tile R in {4, 8, 16}, on scratch copies of Y_d
+ * (the caller's layouts are only read), and returns the fastest R in
+ * *best_tile_rows and, if ms_per_step is not NULL, the three average step
+ * times (ms) in that order.  Leaves the graphs' workspaces planned for R = 16.
+ * Synchronising.  Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d, int32_t count,
+                                      const tsgne_params* p, int32_t steps, int32_t* best_tile_rows,
+                                      double* ms_per_step, void* stream);
+
+/*
  * Per-phase device timing of one graph's kernels, measured with HIP events
  * recorded on the stream each kernel is launched on.  Phases:
  */

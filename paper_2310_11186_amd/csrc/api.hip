@@ -18,8 +18,6 @@ thread_local std::string g_error;
 
 void set_error(const std::string& msg) { g_error = msg; }
 
-namespace {
-
 tsgne_status fail(tsgne_status code, const std::string& msg) {
   set_error(msg);
   return code;
@@ -30,24 +28,7 @@ tsgne_status hip_fail(hipError_t e, const char* what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define TSGNE_HIP(call, what)                      \
-  do {                                             \
-    hipError_t e_ = (call);                        \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
-
-template <typename T>
-hipError_t dalloc(T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-}
-
-template <typename T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
+namespace {
 
 void free_workspace(Workspace& ws) {
   dfree(ws.items);
@@ -83,17 +64,6 @@ void free_graph(tsgne_graph* g) {
   delete g;
 }
 
-// Makes the graph's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 // --- phase timing -----------------------------------------------------------
 
@@ -166,6 +136,8 @@ struct Timed {
   ~Timed() { timer_end(g, idx, s); }
 };
 
+}  // namespace
+
 tsgne_status validate_params(const tsgne_params* p) {
   if (!std::isfinite(p->early_exaggeration) || p->early_exaggeration <= 0.f)
     return fail(TSGNE_E_INVAL, "early_exaggeration must be finite and > 0");
@@ -227,6 +199,8 @@ tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p) {
   }
   return TSGNE_OK;
 }
+
+namespace {
 
 // Repulsion partials, Z, attraction: everything the gradient needs at Y.
 tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipStream_t s) {

@@ -51,6 +51,43 @@ struct Workspace {
   int32_t kl_blocks = 0;
 };
 
+// Per-graph view used by the batched kernels (device memory, one per graph).
+struct BatchDesc {
+  float2* Y;
+  float2* U;
+  float2* G;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* P;
+  float2* part;
+  double* zpart;
+  float* zpart32;
+  double* Z;
+  double2* attract;
+  int64_t n_items;
+  int32_t n;
+  int32_t nb;
+  int32_t n_iter;
+  float eta;
+};
+
+// Launch tables of a batch (all device pointers).
+struct BatchPlan {
+  BatchDesc* descs = nullptr;
+  int4* items = nullptr;          // (graph, a, b, item index within the graph)
+  int2* light_chunks = nullptr;   // (graph, first row) per 32-row block
+  int2* heavy = nullptr;          // (graph, row) per heavy row
+  int2* row_blocks = nullptr;     // (graph, first row) per 256-row block
+  int32_t* t = nullptr;           // step index
+  int64_t n_items = 0;
+  int32_t n_light_chunks = 0;
+  int32_t n_heavy = 0;
+  int32_t n_row_blocks = 0;
+  int32_t count = 0;
+  int32_t R = 0;
+  int32_t T = 0;
+};
+
 // Event-pair timing of kernel phases (see tsgne_graph_set_timing).
 struct PhaseTimer {
   struct Pending {
@@ -89,6 +126,43 @@ namespace tsgne {
 
 // Thread-local error message.
 void set_error(const std::string& msg);
+tsgne_status fail(tsgne_status code, const std::string& msg);
+tsgne_status hip_fail(hipError_t e, const char* what);
+
+#define TSGNE_HIP(call, what)                        \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Makes a device current for the duration of a scope.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+tsgne_status validate_params(const tsgne_params* p);
+float effective_eta(const tsgne_graph* g, const tsgne_params* p);
+tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p);
 
 // Launchers (return hipSuccess or the first HIP error).
 hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, uint32_t* err, int32_t* counters,
@@ -110,6 +184,7 @@ hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gai
                          hipStream_t s);
 hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s);
 hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s);
+hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStream_t s);
 
 // Repulsion plan for n positions (R = 0 picks automatically).
 RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant);

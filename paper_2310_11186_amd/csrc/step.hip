@@ -317,8 +317,8 @@ hipError_t launch_repulsion_r(const Workspace& ws, int32_t n, const float2* Y, i
 constexpr int kZThreads = 1024;
 
 template <bool SPLIT>
-__global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ zpart, const float* __restrict__ zpart32,
-                                                    int64_t n_items, double* __restrict__ Z) {
+__device__ void zsum_block(const double* __restrict__ zpart, const float* __restrict__ zpart32, int64_t n_items,
+                           double* __restrict__ Z) {
   __shared__ double sh64[kZThreads];
   __shared__ float sh32[kZThreads];
   const int t = threadIdx.x;
@@ -339,6 +339,12 @@ __global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ z
     __syncthreads();
   }
   if (t == 0) *Z = SPLIT ? sh64[0] : (double)sh32[0];
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ zpart, const float* __restrict__ zpart32,
+                                                    int64_t n_items, double* __restrict__ Z) {
+  zsum_block<SPLIT>(zpart, zpart32, n_items, Z);
 }
 
 // Attraction sum_j p_ij w_ij (y_i - y_j) over the stored entries of row i
@@ -409,15 +415,13 @@ __global__ __launch_bounds__(kBlock) void k_attract_heavy(const int32_t* __restr
   attract_row<kWave, SPLIT>(row_ptr, col, P, Y, heavy[w], (int)(threadIdx.x & (kWave - 1)), out);
 }
 
-// g_i = 4 (alpha * A_i - R_i / Z), then the momentum/gains update.
+// g_i = 4 (alpha * A_i - R_i / Z), then the momentum/gains update of row i.
 template <bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ part, int32_t nb, int32_t T,
-                                                   const double2* __restrict__ attract, const double* __restrict__ Zp,
-                                                   int32_t n, float2* __restrict__ Y, float2* __restrict__ U,
-                                                   float2* __restrict__ G, float alpha, float momentum, float eta,
-                                                   float min_gain, int do_update, float2* __restrict__ grad_out) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void update_row(const float2* __restrict__ part, int32_t nb, int32_t T,
+                                           const double2* __restrict__ attract, double Z, int32_t i,
+                                           float2* __restrict__ Y, float2* __restrict__ U, float2* __restrict__ G,
+                                           float alpha, float momentum, float eta, float min_gain, bool do_update,
+                                           float2* __restrict__ grad_out) {
   const int32_t k = i / T, off = i - k * T;
   const float2* __restrict__ pp = part + (int64_t)k * nb * T + off;
   double rx = 0.0, ry = 0.0;
@@ -432,7 +436,6 @@ __global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ pa
       sy += v.y;
     }
   }
-  const double Z = *Zp;
   const double2 A = attract[i];
   float2 g;
   if (SPLIT) {
@@ -458,6 +461,101 @@ __global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ pa
   Y[i] = y;
   U[i] = u;
   G[i] = gn;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ part, int32_t nb, int32_t T,
+                                                   const double2* __restrict__ attract, const double* __restrict__ Zp,
+                                                   int32_t n, float2* __restrict__ Y, float2* __restrict__ U,
+                                                   float2* __restrict__ G, float alpha, float momentum, float eta,
+                                                   float min_gain, int do_update, float2* __restrict__ grad_out) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  update_row<SPLIT>(part, nb, T, attract, *Zp, i, Y, U, G, alpha, momentum, eta, min_gain, do_update != 0, grad_out);
+}
+
+// ---------------------------------------------------------------------------
+// Batched step over many graphs.  Every graph keeps its own tiling, item
+// order, partial buffers and reduction order, so a graph advanced inside a
+// batch computes exactly what it computes alone with the same tile size.  The
+// step index t lives in device memory (advanced by the last kernel of a step),
+// so one captured step can be replayed; graphs with t >= n_iter are skipped.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool batch_live(const BatchDesc& d, int32_t t) { return t < d.n_iter; }
+
+template <int R, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_batch_repulse(const BatchDesc* __restrict__ descs,
+                                                          const int4* __restrict__ items, int64_t n_items,
+                                                          const int32_t* __restrict__ tp) {
+  const int64_t item =
+      (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (item >= n_items) return;
+  const int4 it = items[item];
+  const int32_t gi = __builtin_amdgcn_readfirstlane(it.x);
+  const BatchDesc& d = descs[gi];
+  if (!batch_live(d, *tp)) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t a = __builtin_amdgcn_readfirstlane(it.y), b = __builtin_amdgcn_readfirstlane(it.z);
+  const int64_t li = __builtin_amdgcn_readfirstlane(it.w);
+  if (a != b) tile_symmetric<R, SPLIT>(d.Y, d.n, d.nb, a, b, d.part, d.zpart, d.zpart32, li, lane);
+  else tile_diag_light<R, SPLIT>(d.Y, d.n, d.nb, a, d.part, d.zpart, d.zpart32, li, lane);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kZThreads) void k_batch_zsum(const BatchDesc* __restrict__ descs,
+                                                          const int32_t* __restrict__ tp) {
+  const BatchDesc& d = descs[blockIdx.x];
+  if (!batch_live(d, *tp)) return;
+  zsum_block<SPLIT>(d.zpart, d.zpart32, d.n_items, d.Z);
+}
+
+// One block of 256 threads covers 32 light rows of one graph (8 lanes each).
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_batch_attract_light(const BatchDesc* __restrict__ descs,
+                                                                const int2* __restrict__ chunks,
+                                                                const int32_t* __restrict__ tp) {
+  const int2 ch = chunks[blockIdx.x];
+  const BatchDesc& d = descs[ch.x];
+  if (!batch_live(d, *tp)) return;
+  const int32_t i0 = ch.y + (int32_t)(threadIdx.x / kRowLanes);
+  const int32_t i = min(i0, d.n - 1);
+  const bool live = i0 < d.n && (d.row_ptr[i + 1] - d.row_ptr[i]) <= kHeavyDegree;
+  if (live) attract_row<kRowLanes, SPLIT>(d.row_ptr, d.col, d.P, d.Y, i, (int)(threadIdx.x & (kRowLanes - 1)),
+                                          d.attract);
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_batch_attract_heavy(const BatchDesc* __restrict__ descs,
+                                                                const int2* __restrict__ heavy, int32_t n_heavy,
+                                                                const int32_t* __restrict__ tp) {
+  const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
+  if (w >= n_heavy) return;
+  const int2 hr = heavy[w];
+  const BatchDesc& d = descs[hr.x];
+  if (!batch_live(d, *tp)) return;
+  attract_row<kWave, SPLIT>(d.row_ptr, d.col, d.P, d.Y, hr.y, (int)(threadIdx.x & (kWave - 1)), d.attract);
+}
+
+// One block of 256 threads covers 256 rows of one graph.
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_batch_update(const BatchDesc* __restrict__ descs,
+                                                         const int2* __restrict__ blocks, const int32_t* __restrict__ tp,
+                                                         int32_t T, float ee, int32_t t_ee, float m_early, float m_late,
+                                                         float min_gain) {
+  const int2 bl = blocks[blockIdx.x];
+  const BatchDesc& d = descs[bl.x];
+  const int32_t t = *tp;
+  if (!batch_live(d, t)) return;
+  const int32_t i = bl.y + (int32_t)threadIdx.x;
+  if (i >= d.n) return;
+  const bool early = t < t_ee;
+  update_row<SPLIT>(d.part, d.nb, T, d.attract, *d.Z, i, d.Y, d.U, d.G, early ? ee : 1.0f, early ? m_early : m_late,
+                    d.eta, min_gain, true, nullptr);
+}
+
+__global__ void k_batch_advance(int32_t* __restrict__ tp) {
+  if (threadIdx.x == 0) *tp += 1;
 }
 
 // KL = sum_e P_e log(P_e / q_e), q_e = w_e / Z, in FP64: fixed grid, strided
@@ -595,6 +693,63 @@ hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kKLThreads), 0, s, ws.klpart, ws.kl_blocks, ws.klout);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_batch_repulse_r(const BatchPlan& bp, bool split, hipStream_t s) {
+  const dim3 grid((unsigned)((bp.n_items + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (split)
+    hipLaunchKernelGGL((k_batch_repulse<R, true>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items, bp.t);
+  else
+    hipLaunchKernelGGL((k_batch_repulse<R, false>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items, bp.t);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStream_t s) {
+  const bool split = p.precision != TSGNE_PREC_FP32;
+  hipError_t e = hipSuccess;
+  if (bp.n_items > 0) {
+    switch (bp.R) {
+      case 4: e = launch_batch_repulse_r<4>(bp, split, s); break;
+      case 8: e = launch_batch_repulse_r<8>(bp, split, s); break;
+      case 16: e = launch_batch_repulse_r<16>(bp, split, s); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  if (split) hipLaunchKernelGGL(k_batch_zsum<true>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs, bp.t);
+  else hipLaunchKernelGGL(k_batch_zsum<false>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs, bp.t);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (bp.n_light_chunks > 0) {
+    if (split)
+      hipLaunchKernelGGL(k_batch_attract_light<true>, dim3(bp.n_light_chunks), dim3(kBlock), 0, s, bp.descs,
+                         bp.light_chunks, bp.t);
+    else
+      hipLaunchKernelGGL(k_batch_attract_light<false>, dim3(bp.n_light_chunks), dim3(kBlock), 0, s, bp.descs,
+                         bp.light_chunks, bp.t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (bp.n_heavy > 0) {
+    const unsigned hb = blocks_for(bp.n_heavy, kWavesPerBlock);
+    if (split)
+      hipLaunchKernelGGL(k_batch_attract_heavy<true>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy,
+                         bp.t);
+    else
+      hipLaunchKernelGGL(k_batch_attract_heavy<false>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy,
+                         bp.t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (split)
+    hipLaunchKernelGGL(k_batch_update<true>, dim3(bp.n_row_blocks), dim3(kBlock), 0, s, bp.descs, bp.row_blocks, bp.t,
+                       bp.T, p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late,
+                       p.min_gain);
+  else
+    hipLaunchKernelGGL(k_batch_update<false>, dim3(bp.n_row_blocks), dim3(kBlock), 0, s, bp.descs, bp.row_blocks,
+                       bp.t, bp.T, p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late,
+                       p.min_gain);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, bp.t);
   return hipGetLastError();
 }
 

@@ -222,6 +222,24 @@ def make(name: str, seed: int | None = None) -> GraphInput:
     raise KeyError(name)
 
 
+def batch_workload(count: int = 256, seed: int | None = None, n_min: int = 500, n_max: int = 50_000,
+                   d: int = 64) -> list[GraphInput]:
+    """Many independent SBM graphs: node counts log-uniform in [n_min, n_max],
+    average degree uniform in [3, 8], 4-40 equal communities each, mixing 0.18,
+    d-dim embeddings (community centre + N(0, 0.25 I))."""
+    s = MASTER_SEED + 4 if seed is None else seed
+    rng = _rng(s, 9)
+    out = []
+    for k in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        avg = float(rng.uniform(3.0, 8.0))
+        comm = int(rng.integers(4, 41))
+        edges, labels = sbm_sparse(n, min(comm, n // 2), avg, 0.18, s * 1000 + k)
+        X = embedding(labels, d, 0.5, s * 1000 + k)
+        out.append(GraphInput(n, edges, labels, X, initial_layout(n, s * 1000 + k), "batch%d" % k))
+    return out
+
+
 def small_sbm(n: int, n_comm: int, avg_deg: float, d: int, seed: int, mu: float = 0.18) -> GraphInput:
     """A small seeded SBM test case with a given size and average degree."""
     edges, labels = sbm_sparse(n, n_comm, avg_deg, mu, seed)

@@ -35,7 +35,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
-    "tsgne_kl", "tsgne_graph_set_timing", "tsgne_graph_timing",
+    "tsgne_kl", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
 )
 
 TSGNE_PHASES = ("repulsion", "zsum", "attract", "update", "kl")
@@ -92,6 +92,9 @@ def lib():
             "tsgne_step": (st, [vp, vp, vp, vp, i32, P, vp, vp, vp]),
             "tsgne_run": (st, [vp, vp, i32, P, vp, vp]),
             "tsgne_kl": (st, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_batch_run": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32), i32, P, vp]),
+            "tsgne_autotune": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double), vp]),
             "tsgne_graph_set_timing": (st, [vp, i32]),
             "tsgne_graph_timing": (st, [vp, ctypes.POINTER(tsgne_timing)]),
         }
@@ -279,3 +282,30 @@ def tsgne_kl(g: Graph, Y, stream=None) -> float:
     out = ctypes.c_double(0.0)
     _check(lib().tsgne_kl(g.handle, _ptr(Y), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def tsgne_batch_run(graphs, Ys, n_iter, params: tsgne_params, stream=None) -> None:
+    """Advances graphs[k] (Graph) on layouts Ys[k] (float32[n_k, 2] device) by
+    n_iter[k] steps together (one captured step replayed for the batch)."""
+    import torch
+    count = len(graphs)
+    if len(Ys) != count or len(n_iter) != count:
+        raise ValueError("graphs, Ys and n_iter must have the same length")
+    for g, Y in zip(graphs, Ys):
+        _require(Y, torch.float32, (g.info()[0], 2), "Y")
+    hs = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+    ys = (ctypes.c_void_p * count)(*[Y.data_ptr() for Y in Ys])
+    it = (ctypes.c_int32 * count)(*[int(k) for k in n_iter])
+    _check(lib().tsgne_batch_run(hs, ys, it, count, ctypes.byref(params), _stream(stream)))
+
+
+def tsgne_autotune(graphs, Ys, params: tsgne_params, steps: int = 3, stream=None) -> tuple[int, list]:
+    """(fastest tile_rows, [ms per step for tile_rows 4, 8, 16]) for this batch."""
+    count = len(graphs)
+    hs = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+    ys = (ctypes.c_void_p * count)(*[Y.data_ptr() for Y in Ys])
+    best = ctypes.c_int32(0)
+    ms = (ctypes.c_double * 3)()
+    _check(lib().tsgne_autotune(hs, ys, count, ctypes.byref(params), int(steps), ctypes.byref(best), ms,
+                                _stream(stream)))
+    return best.value, list(ms)

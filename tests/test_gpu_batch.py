@@ -1,0 +1,82 @@
+"""Batched optimisation (tsgne_batch_run) and the tile autotuner, through the
+C-ABI.  A graph advanced inside a batch must equal the same graph run alone
+with the same tile size, bit for bit; the batch replays a captured step many
+times between eager work, and every graph is checked after it."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_11186_amd import synth, tsgne
+
+pytestmark = pytest.mark.gpu
+
+
+def upload(gi, gpu):
+    import torch
+    rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
+    g = tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                            torch.from_numpy(gi.X).to(gpu), 30.0)
+    return g
+
+
+def small_batch(seed=0):
+    sizes = [300, 700, 1500, 2600, 257, 1031]
+    return [synth.small_sbm(n, 3, 5.0, 8, seed * 100 + k) for k, n in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("R", [4, 8])
+def test_batch_equals_alone_bitwise(gpu, R):
+    import torch
+    gis = small_batch(1)
+    graphs = [upload(gi, gpu) for gi in gis]
+    n_iter = [60, 35, 51, 60, 7, 26]
+    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0, tile_rows=R,
+                                   repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC)
+    Ys = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    tsgne.tsgne_batch_run(graphs, Ys, n_iter, p)
+    for gi, g, Yb, k in zip(gis, graphs, Ys, n_iter):
+        Ya = torch.from_numpy(gi.Y0).to(gpu)
+        tsgne.tsgne_run(g, Ya, k, p)
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yb), gi.n
+
+
+def test_batch_matches_oracle(gpu):
+    import torch
+    gis = small_batch(2)[:3]
+    graphs = [upload(gi, gpu) for gi in gis]
+    p = tsgne.tsgne_params_default(exaggeration_iters=10, learning_rate=40.0)
+    Ys = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    tsgne.tsgne_batch_run(graphs, Ys, [20, 20, 20], p)
+    for gi, Y in zip(gis, Ys):
+        rp, col = oracle.csr_from_edges(gi.n, gi.edges)
+        P, _ = oracle.build_P(rp, col, gi.X, 30.0)
+        oY, _, _, _ = oracle.run(rp, col, P, gi.Y0, n_steps=20, exaggeration_iters=10, eta=40.0)
+        err = np.linalg.norm(Y.cpu().numpy() - oY) / np.linalg.norm(oY)
+        assert err <= 1e-4, (gi.n, err)
+
+
+def test_autotune_picks_a_tile_and_leaves_inputs(gpu):
+    import torch
+    gis = small_batch(3)
+    graphs = [upload(gi, gpu) for gi in gis]
+    Ys = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    before = [Y.clone() for Y in Ys]
+    best, ms = tsgne.tsgne_autotune(graphs, Ys, tsgne.tsgne_params_default(), steps=2)
+    assert best in (4, 8, 16)
+    assert all(m > 0 for m in ms) and ms[(4, 8, 16).index(best)] == min(ms)
+    for a, b in zip(Ys, before):
+        assert torch.equal(a, b)
+
+
+def test_batch_rejects_bad_arguments(gpu):
+    import torch
+    gi = synth.small_sbm(400, 2, 4.0, 4, 9)
+    g = upload(gi, gpu)
+    Y = torch.from_numpy(gi.Y0).to(gpu)
+    p = tsgne.tsgne_params_default()
+    with pytest.raises(tsgne.TsgneError) as e:
+        tsgne.tsgne_batch_run([g, g], [Y, Y.clone()], [5, 5], p)
+    assert e.value.status == tsgne.TSGNE_E_INVAL
+    with pytest.raises(tsgne.TsgneError):
+        tsgne.tsgne_batch_run([g], [Y], [-1], p)
