@@ -190,12 +190,83 @@ def run_batch(args) -> int:
     return 0
 
 
+def serve_stream(srv_kwargs, reqs, arrivals, n_iter):
+    """Submits reqs at the given arrival times (s) and waits for all; returns the
+    server's statistics and the wall time."""
+    from paper_2310_11186_amd import tsgne
+    srv = tsgne.Server(**srv_kwargs)
+    t0 = time.perf_counter()
+    tickets = []
+    for gi, at in zip(reqs, arrivals):
+        delay = at - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, n_iter))
+    statuses = [srv.wait(t)[0] for t in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    if any(s != tsgne.TSGNE_OK for s in statuses):
+        raise RuntimeError("a served request failed: %s" % statuses)
+    return st, wall
+
+
+def run_serve(args) -> int:
+    """Serving: layout requests with Poisson arrivals at 0.8x the measured
+    saturated rate, continuous batching against one request at a time."""
+    import numpy as np
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    count = args.requests
+    n_iter = args.n_iter if args.n_iter is not None else 500
+    log("generating %d requests" % count)
+    reqs = synth.serving_requests(count)
+    params = tsgne.tsgne_params_default(exaggeration_iters=n_iter // 4)
+    kw = dict(max_active=64, steps_per_round=64, round_ms=25.0, tile_rows=args.tile_rows or 8, params=params)
+    kw1 = dict(kw, max_active=1)
+    # saturated rate: everything submitted at once
+    st_sat, wall_sat = serve_stream(kw, reqs, [0.0] * count, n_iter)
+    sat_rate = count / wall_sat
+    log("saturated: %.2f layouts/s" % sat_rate)
+    st_sat1, wall_sat1 = serve_stream(kw1, reqs, [0.0] * count, n_iter)
+    log("saturated, one at a time: %.2f layouts/s" % (count / wall_sat1))
+    qps = 0.8 * sat_rate
+    rng = np.random.default_rng(2310_11186)
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=count))
+    st, wall = serve_stream(kw, reqs, arrivals, n_iter)
+    log("served at %.2f req/s: p50 %.0f ms, p99 %.0f ms" % (qps, st["latency_p50_ms"], st["latency_p99_ms"]))
+    st1, wall1 = serve_stream(kw1, reqs, arrivals, n_iter)
+    log("one at a time: p50 %.0f ms, p99 %.0f ms" % (st1["latency_p50_ms"], st1["latency_p99_ms"]))
+    pairs = sum(float(gi.n) * (gi.n - 1) for gi in reqs) * n_iter
+    result = {
+        "metric": "served layouts/s with p50/p99 latency (Poisson arrivals, continuous batching)",
+        "value": count / wall, "unit": "layouts/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (FP64 Z/KL/cross-tile sums)", "data": "synthetic",
+        "config": {"workload": "serve", "requests": count, "n_iter": n_iter, "qps": qps,
+                   "nodes_range": [1000, 200000], "nodes_total": int(sum(gi.n for gi in reqs)),
+                   "tile_rows": kw["tile_rows"], "steps_per_round": kw["steps_per_round"],
+                   "round_ms": kw["round_ms"], "max_active": kw["max_active"]},
+        "latency_p50_ms": st["latency_p50_ms"], "latency_p99_ms": st["latency_p99_ms"],
+        "pair_interactions_per_s": pairs / wall,
+        "saturated": {"layouts_per_s": sat_rate, "seconds": wall_sat,
+                      "one_at_a_time_layouts_per_s": count / wall_sat1,
+                      "speedup_vs_one_at_a_time": wall_sat1 / wall_sat},
+        "one_at_a_time": {"layouts_per_s": count / wall1, "latency_p50_ms": st1["latency_p50_ms"],
+                          "latency_p99_ms": st1["latency_p99_ms"], "seconds": wall1},
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k or batch256")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256 or serve")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
     ap.add_argument("--repulsion", default="auto", choices=["auto", "direct", "symmetric"])
     ap.add_argument("--tile-rows", type=int, default=0)
@@ -218,6 +289,8 @@ def main() -> int:
 
     if args.workload == "batch256":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

@@ -50,7 +50,8 @@ typedef int32_t tsgne_status;
 #define TSGNE_E_NOMEM (-3)     /* device or host allocation failed */
 #define TSGNE_E_DEVICE (-4)    /* a HIP runtime call failed */
 #define TSGNE_E_NONFINITE (-5) /* a non-finite value appeared in the layout */
-#define TSGNE_E_BUSY (-6)      /* resource busy (queue full) */
+#define TSGNE_E_BUSY (-6)      /* resource busy (queue full, request still running) */
+#define TSGNE_E_CANCELLED (-7) /* the request was cancelled */
 
 /* Precision modes of the per-step arithmetic. */
 #define TSGNE_PREC_SPLIT 0 /* FP32 pair arithmetic; FP64 for Z, cross-tile force sums, KL */
@@ -221,6 +222,88 @@ TSGNE_API tsgne_status tsgne_batch_run(tsgne_graph* const* graphs, float* const*
 TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d, int32_t count,
                                       const tsgne_params* p, int32_t steps, int32_t* best_tile_rows,
                                       double* ms_per_step, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Layout server: continuous batching of independent layout requests on the
+ * current device.  Requests are copied in at submission and queued; a worker
+ * thread admits them while their estimated device footprint fits the budget
+ * (building P on admission), advances the active requests in rounds of one
+ * batched, graph-captured launch sequence (each request at its own step
+ * index), and completes requests that reach n_iter (layout copied out, device
+ * memory released).  With round_ms > 0 each round aims at that much GPU time
+ * and gives every active request an equal share of it as steps (at least 1,
+ * at most steps_per_round): small graphs take many steps per round, large ones
+ * few, so small requests are not held back by large ones.  With round_ms <= 0
+ * every active request takes steps_per_round steps per round.  Each request's
+ * arithmetic depends only on itself and tile_rows: its layout equals
+ * tsgne_run of the same graph alone with that tile_rows and the symmetric
+ * repulsion, bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct tsgne_server tsgne_server;
+
+typedef struct tsgne_server_config {
+  int64_t hbm_budget;      /* device bytes the server may hold; 0 = 80 % of the free memory */
+  int32_t max_active;      /* requests advanced together (default 64) */
+  int32_t max_queue;       /* waiting requests before submit returns E_BUSY */
+  int32_t steps_per_round; /* most steps a request takes per round (default 64) */
+  int32_t tile_rows;       /* repulsion tile of every request: 4, 8 (default) or 16 */
+  tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
+  float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
+} tsgne_server_config;
+
+typedef struct tsgne_request {
+  int32_t n;             /* nodes */
+  int64_t m;             /* undirected edges in edges_h */
+  const int32_t* edges_h;/* int32[m][2], host; made canonical by the server (tsgne_csr_from_edges) */
+  int32_t d;             /* embedding dimension */
+  const float* X_h;      /* float32[n][d], host */
+  const float* Y0_h;     /* float32[n][2], host */
+  float perplexity;      /* > 1 */
+  int32_t n_iter;        /* optimisation steps */
+} tsgne_request;
+
+typedef struct tsgne_server_stats {
+  int64_t submitted, completed, failed, cancelled;
+  int32_t queued, active;
+  int64_t hbm_in_use, hbm_budget; /* bytes (estimated footprints) */
+  int64_t rounds;
+  double busy_s;                  /* time spent in rounds */
+  double latency_p50_ms, latency_p99_ms, latency_mean_ms; /* submission to completion, completed requests */
+  double layouts_per_s;           /* completed / (last completion - first submission) */
+} tsgne_server_stats;
+
+TSGNE_API void tsgne_server_config_default(tsgne_server_config* c);
+
+/* Starts a server (and its worker thread) on the current device.
+ * Errors: E_INVAL (bad configuration), E_DEVICE, E_NOMEM. */
+TSGNE_API tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** out);
+
+/* Copies the request in and queues it; *ticket identifies it.  Errors: E_INVAL
+ * (bad sizes, null buffers), E_NOMEM (its footprint exceeds the whole budget),
+ * E_BUSY (queue full).  Graph errors (non-canonical edges are canonicalised;
+ * endpoints out of range) surface as the request's result. */
+TSGNE_API tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* req, uint64_t* ticket);
+
+/* Non-blocking: *done = 1 when the request has finished; then *result holds its
+ * status (TSGNE_OK, E_NONFINITE, E_CANCELLED, ...) and, if TSGNE_OK and Y_h
+ * is not NULL, float32[n][2] receives the layout. */
+TSGNE_API tsgne_status tsgne_server_poll(tsgne_server* srv, uint64_t ticket, float* Y_h, int32_t* done,
+                                         tsgne_status* result);
+
+/* Blocks until the request has finished; outputs as tsgne_server_poll. */
+TSGNE_API tsgne_status tsgne_server_wait(tsgne_server* srv, uint64_t ticket, float* Y_h, tsgne_status* result);
+
+/* Forgets a finished request (its layout copy is released).  E_BUSY if running. */
+TSGNE_API tsgne_status tsgne_server_release(tsgne_server* srv, uint64_t ticket);
+
+/* Cancels a queued request at once, an active one at the next round boundary. */
+TSGNE_API tsgne_status tsgne_server_cancel(tsgne_server* srv, uint64_t ticket);
+
+TSGNE_API tsgne_status tsgne_server_get_stats(tsgne_server* srv, tsgne_server_stats* out);
+
+/* Stops the worker after its current round, cancels unfinished requests and
+ * frees everything.  NULL is accepted. */
+TSGNE_API tsgne_status tsgne_server_destroy(tsgne_server* srv);
 
 /*
  * Per-phase device timing of one graph's kernels, measured with HIP events

@@ -2,7 +2,7 @@
 // per step for the whole batch, captured once as a HIP graph and replayed, and
 // the autotuner that picks the repulsion tile for a batch by timing it.
 #include <algorithm>
-#include <chrono>
+#include <climits>
 #include <cmath>
 #include <set>
 #include <string>
@@ -11,133 +11,167 @@
 #include "internal.h"
 
 namespace tsgne {
+
+constexpr int kBatchBlockRows = 256;  // rows per update block; attraction blocks cover 1/8 of that
+
+BatchRun::~BatchRun() {
+  if (tables_) (void)hipFree(tables_);
+}
+
+tsgne_status BatchRun::setup(const BatchMember* m, int32_t count, int32_t R, const tsgne_params* p) {
+  tsgne_params pr = *p;
+  pr.tile_rows = R;
+  pr.repulsion = TSGNE_REPULSION_SYMMETRIC;
+  for (int32_t k = 0; k < count; ++k)
+    if (tsgne_status st = ensure_workspace(m[k].g, &pr)) return st;
+  bp_ = BatchPlan{};
+  bp_.count = count;
+  bp_.R = R;
+  bp_.T = kWave * R;
+  std::vector<BatchDesc> descs((size_t)count);
+  std::vector<int4> diag_items, items;
+  std::vector<int2> chunks, heavy, blocks;
+  for (int32_t k = 0; k < count; ++k) {
+    tsgne_graph* g = m[k].g;
+    const Workspace& ws = g->ws;
+    BatchDesc& d = descs[(size_t)k];
+    d.Y = reinterpret_cast<float2*>(m[k].Y);
+    d.U = reinterpret_cast<float2*>(m[k].U);
+    d.G = reinterpret_cast<float2*>(m[k].G);
+    d.row_ptr = g->row_ptr;
+    d.col = g->col;
+    d.P = g->P;
+    d.part = ws.part;
+    d.zpart = ws.zpart;
+    d.zpart32 = ws.zpart32;
+    d.Z = ws.Z;
+    d.attract = ws.attract;
+    d.t = m[k].t;
+    d.limit = m[k].limit;
+    d.n_items = ws.plan.items;
+    d.n = g->n;
+    d.nb = ws.plan.nb;
+    d.n_iter = m[k].n_iter;
+    d.eta = effective_eta(g, p);
+    // items in the graph's own order (the Z partial slot is the local index)
+    int64_t li = 0;
+    for (int32_t a = 0; a < ws.plan.nb; ++a)
+      for (int32_t b = a; b < ws.plan.nb; ++b, ++li) (a == b ? diag_items : items).push_back(make_int4(k, a, b, (int)li));
+    for (int32_t r = 0; r < g->n; r += kBatchBlockRows / 8) chunks.push_back(make_int2(k, r));
+    for (int32_t r = 0; r < g->n; r += kBatchBlockRows) blocks.push_back(make_int2(k, r));
+    if (g->n_heavy > 0) {
+      std::vector<int32_t> h((size_t)g->n_heavy);
+      TSGNE_HIP(hipMemcpy(h.data(), g->heavy, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost), "read heavy rows");
+      for (int32_t r : h) heavy.push_back(make_int2(k, r));
+    }
+  }
+  // diagonal tiles (one row per lane per pass, the slower kind) go first
+  diag_items.insert(diag_items.end(), items.begin(), items.end());
+  bp_.n_items = (int64_t)diag_items.size();
+  bp_.n_light_chunks = (int32_t)chunks.size();
+  bp_.n_heavy = (int32_t)heavy.size();
+  bp_.n_row_blocks = (int32_t)blocks.size();
+
+  const size_t b_descs = sizeof(BatchDesc) * descs.size();
+  const size_t b_items = sizeof(int4) * diag_items.size();
+  const size_t b_chunks = sizeof(int2) * chunks.size();
+  const size_t b_heavy = sizeof(int2) * heavy.size();
+  const size_t b_blocks = sizeof(int2) * blocks.size();
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t total = up(b_descs) + up(b_items) + up(b_chunks) + up(b_heavy) + up(b_blocks);
+  if (tables_) (void)hipFree(tables_);
+  tables_ = nullptr;
+  TSGNE_HIP(hipMalloc(&tables_, total), "allocate batch tables");
+  char* base = static_cast<char*>(tables_);
+  size_t at = 0;
+  auto place = [&](size_t bytes) {
+    char* q = base + at;
+    at += up(bytes);
+    return q;
+  };
+  bp_.descs = reinterpret_cast<BatchDesc*>(place(b_descs));
+  bp_.items = reinterpret_cast<int4*>(place(b_items));
+  bp_.light_chunks = reinterpret_cast<int2*>(place(b_chunks));
+  bp_.heavy = reinterpret_cast<int2*>(place(b_heavy));
+  bp_.row_blocks = reinterpret_cast<int2*>(place(b_blocks));
+  TSGNE_HIP(hipMemcpy(bp_.descs, descs.data(), b_descs, hipMemcpyHostToDevice), "upload batch descriptors");
+  if (b_items) TSGNE_HIP(hipMemcpy(bp_.items, diag_items.data(), b_items, hipMemcpyHostToDevice), "upload items");
+  if (b_chunks) TSGNE_HIP(hipMemcpy(bp_.light_chunks, chunks.data(), b_chunks, hipMemcpyHostToDevice), "upload rows");
+  if (b_heavy) TSGNE_HIP(hipMemcpy(bp_.heavy, heavy.data(), b_heavy, hipMemcpyHostToDevice), "upload heavy rows");
+  if (b_blocks) TSGNE_HIP(hipMemcpy(bp_.row_blocks, blocks.data(), b_blocks, hipMemcpyHostToDevice), "upload blocks");
+  return TSGNE_OK;
+}
+
+tsgne_status run_batch_steps(const BatchRun& br, const tsgne_params* p, int32_t n_steps, int32_t chunk,
+                             hipStream_t s) {
+  if (n_steps <= 0) return TSGNE_OK;
+  chunk = std::max(1, std::min(chunk, n_steps));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  TSGNE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t le = hipSuccess;
+  for (int32_t k = 0; k < chunk && le == hipSuccess; ++k) le = launch_batch_step(br.plan(), *p, s);
+  hipError_t ce = hipStreamEndCapture(s, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(le, "launch batched step during capture");
+  }
+  TSGNE_HIP(ce, "end capture");
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "instantiate batch graph");
+  }
+  const int32_t replays = (n_steps + chunk - 1) / chunk;
+  for (int32_t r = 0; r < replays && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
+  hipError_t se = hipStreamSynchronize(s);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  TSGNE_HIP(e, "launch batch graph");
+  TSGNE_HIP(se, "synchronise batch");
+  return TSGNE_OK;
+}
+
 namespace {
 
 constexpr int kCaptureSteps = 25;  // steps per captured HIP graph
 
-// Device buffers of one batch: launch tables and per-graph optimiser state.
-struct BatchRun {
-  BatchPlan bp;
-  std::vector<tsgne_graph*> graphs;
-  float* state = nullptr;     // U and gains of every graph, contiguous
-  void* tables = nullptr;     // descs, items, chunks, heavy, row blocks, t
-  int32_t max_iter = 0;
-
-  ~BatchRun() {
-    dfree(state);
-    if (tables) (void)hipFree(tables);
+// Optimiser state (U = 0, gains = 1, t = 0, no pause limit) for a list of
+// graphs, contiguous.
+struct PooledState {
+  float* f = nullptr;
+  int32_t* t = nullptr;  // [count] step indices, then [count] limits
+  ~PooledState() {
+    dfree(f);
+    dfree(t);
   }
-
-  // R: rows per lane of the repulsion tile, shared by the whole batch.
-  tsgne_status setup(tsgne_graph* const* gs, float* const* Ys, const int32_t* n_iter, int32_t count, int32_t R,
-                     const tsgne_params* p, hipStream_t s) {
-    graphs.assign(gs, gs + count);
-    tsgne_params pr = *p;
-    pr.tile_rows = R;
-    pr.repulsion = TSGNE_REPULSION_SYMMETRIC;
-    int64_t total_n = 0;
-    for (int32_t k = 0; k < count; ++k) {
-      if (tsgne_status st = ensure_workspace(gs[k], &pr)) return st;
-      total_n += gs[k]->n;
-      max_iter = std::max(max_iter, n_iter[k]);
-    }
-    bp.count = count;
-    bp.R = R;
-    bp.T = kWave * R;
-
-    // optimiser state: U = 0, gains = 1
-    TSGNE_HIP(dalloc(&state, (size_t)4 * total_n), "allocate batch state");
-    std::vector<BatchDesc> descs((size_t)count);
-    std::vector<int4> diag_items, items;
-    std::vector<int2> chunks, heavy, blocks;
+  tsgne_status make(tsgne_graph* const* gs, float* const* Ys, const int32_t* n_iter, int32_t count,
+                    std::vector<BatchMember>& out, hipStream_t s) {
+    int64_t total = 0;
+    for (int32_t k = 0; k < count; ++k) total += gs[k]->n;
+    TSGNE_HIP(dalloc(&f, (size_t)4 * total), "allocate batch state");
+    TSGNE_HIP(dalloc(&t, 2 * (size_t)count), "allocate step indices");
+    std::vector<float> init((size_t)4 * total, 0.0f);
+    std::fill(init.begin() + 2 * total, init.end(), 1.0f);
+    std::vector<int32_t> ti(2 * (size_t)count, 0);
+    std::fill(ti.begin() + count, ti.end(), INT32_MAX);
+    TSGNE_HIP(hipMemcpyAsync(f, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice, s),
+              "initialise batch state");
+    TSGNE_HIP(hipMemcpyAsync(t, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice, s),
+              "reset step indices");
+    TSGNE_HIP(hipStreamSynchronize(s), "synchronise batch set-up");
+    out.resize((size_t)count);
     int64_t off = 0;
     for (int32_t k = 0; k < count; ++k) {
-      tsgne_graph* g = gs[k];
-      const Workspace& ws = g->ws;
-      BatchDesc& d = descs[(size_t)k];
-      d.Y = reinterpret_cast<float2*>(Ys[k]);
-      d.U = reinterpret_cast<float2*>(state + 2 * off);
-      d.G = reinterpret_cast<float2*>(state + 2 * total_n + 2 * off);
-      d.row_ptr = g->row_ptr;
-      d.col = g->col;
-      d.P = g->P;
-      d.part = ws.part;
-      d.zpart = ws.zpart;
-      d.zpart32 = ws.zpart32;
-      d.Z = ws.Z;
-      d.attract = ws.attract;
-      d.n_items = ws.plan.items;
-      d.n = g->n;
-      d.nb = ws.plan.nb;
-      d.n_iter = n_iter[k];
-      d.eta = effective_eta(g, p);
-      off += g->n;
-      // items in the graph's own order (the Z partial slot is the local index)
-      int64_t li = 0;
-      for (int32_t a = 0; a < ws.plan.nb; ++a)
-        for (int32_t b = a; b < ws.plan.nb; ++b, ++li) (a == b ? diag_items : items).push_back(make_int4(k, a, b, (int)li));
-      for (int32_t r = 0; r < g->n; r += kBlockRows / 8) chunks.push_back(make_int2(k, r));
-      for (int32_t r = 0; r < g->n; r += kBlockRows) blocks.push_back(make_int2(k, r));
-      if (g->n_heavy > 0) {
-        std::vector<int32_t> h((size_t)g->n_heavy);
-        TSGNE_HIP(hipMemcpy(h.data(), g->heavy, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost), "read heavy rows");
-        for (int32_t r : h) heavy.push_back(make_int2(k, r));
-      }
+      out[(size_t)k] = BatchMember{gs[k], Ys[k], f + 2 * off, f + 2 * total + 2 * off, t + k, t + count + k,
+                                   n_iter[k]};
+      off += gs[k]->n;
     }
-    // diagonal tiles (one row per lane per pass, the slower kind) go first
-    diag_items.insert(diag_items.end(), items.begin(), items.end());
-    bp.n_items = (int64_t)diag_items.size();
-    bp.n_light_chunks = (int32_t)chunks.size();
-    bp.n_heavy = (int32_t)heavy.size();
-    bp.n_row_blocks = (int32_t)blocks.size();
-
-    const size_t b_descs = sizeof(BatchDesc) * descs.size();
-    const size_t b_items = sizeof(int4) * diag_items.size();
-    const size_t b_chunks = sizeof(int2) * chunks.size();
-    const size_t b_heavy = sizeof(int2) * heavy.size();
-    const size_t b_blocks = sizeof(int2) * blocks.size();
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t total = up(b_descs) + up(b_items) + up(b_chunks) + up(b_heavy) + up(b_blocks) + 256;
-    TSGNE_HIP(hipMalloc(&tables, total), "allocate batch tables");
-    char* base = static_cast<char*>(tables);
-    size_t at = 0;
-    auto place = [&](size_t bytes) {
-      char* q = base + at;
-      at += up(bytes);
-      return q;
-    };
-    bp.descs = reinterpret_cast<BatchDesc*>(place(b_descs));
-    bp.items = reinterpret_cast<int4*>(place(b_items));
-    bp.light_chunks = reinterpret_cast<int2*>(place(b_chunks));
-    bp.heavy = reinterpret_cast<int2*>(place(b_heavy));
-    bp.row_blocks = reinterpret_cast<int2*>(place(b_blocks));
-    bp.t = reinterpret_cast<int32_t*>(place(sizeof(int32_t)));
-    TSGNE_HIP(hipMemcpy(bp.descs, descs.data(), b_descs, hipMemcpyHostToDevice), "upload batch descriptors");
-    if (b_items) TSGNE_HIP(hipMemcpy(bp.items, diag_items.data(), b_items, hipMemcpyHostToDevice), "upload items");
-    if (b_chunks) TSGNE_HIP(hipMemcpy(bp.light_chunks, chunks.data(), b_chunks, hipMemcpyHostToDevice), "upload rows");
-    if (b_heavy) TSGNE_HIP(hipMemcpy(bp.heavy, heavy.data(), b_heavy, hipMemcpyHostToDevice), "upload heavy rows");
-    if (b_blocks) TSGNE_HIP(hipMemcpy(bp.row_blocks, blocks.data(), b_blocks, hipMemcpyHostToDevice), "upload blocks");
-    return reset(s);
-  }
-
-  // U = 0, gains = 1, t = 0 (plain copies, outside any capture).
-  tsgne_status reset(hipStream_t s) {
-    int64_t total_n = 0;
-    for (tsgne_graph* g : graphs) total_n += g->n;
-    std::vector<float> init((size_t)4 * total_n, 0.0f);
-    std::fill(init.begin() + 2 * total_n, init.end(), 1.0f);
-    TSGNE_HIP(hipMemcpyAsync(state, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice, s),
-              "initialise batch state");
-    const int32_t zero = 0;
-    TSGNE_HIP(hipMemcpyAsync(bp.t, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s), "reset step index");
-    TSGNE_HIP(hipStreamSynchronize(s), "synchronise batch set-up");
     return TSGNE_OK;
   }
-
-  static constexpr int kBlockRows = 256;
 };
 
-tsgne_status check_batch_args(tsgne_graph* const* gs, float* const* Ys, int32_t count, const tsgne_params* p) {
+tsgne_status check_batch_args(tsgne_graph* const* gs, const float* const* Ys, int32_t count, const tsgne_params* p) {
   if (!gs || !Ys || !p) return fail(TSGNE_E_INVAL, "null pointer");
   if (count < 1) return fail(TSGNE_E_INVAL, "count must be >= 1");
   if (tsgne_status st = validate_params(p)) return st;
@@ -180,37 +214,6 @@ struct CaptureStream {
   }
 };
 
-// Runs n steps of the batch: captures kCaptureSteps steps once, replays it.
-tsgne_status run_captured(BatchRun& br, const tsgne_params* p, int32_t n_steps, hipStream_t s) {
-  if (n_steps <= 0) return TSGNE_OK;
-  const int32_t chunk = std::min(kCaptureSteps, n_steps);
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  TSGNE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-  hipError_t le = hipSuccess;
-  for (int32_t k = 0; k < chunk && le == hipSuccess; ++k) le = launch_batch_step(br.bp, *p, s);
-  hipError_t ce = hipStreamEndCapture(s, &graph);
-  if (le != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return hip_fail(le, "launch batched step during capture");
-  }
-  TSGNE_HIP(ce, "end capture");
-  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return hip_fail(e, "instantiate batch graph");
-  }
-  // graphs past their n_iter skip their work, so the last replay may overrun
-  const int32_t replays = (n_steps + chunk - 1) / chunk;
-  for (int32_t r = 0; r < replays && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
-  hipError_t se = hipStreamSynchronize(s);
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  TSGNE_HIP(e, "launch batch graph");
-  TSGNE_HIP(se, "synchronise batch");
-  return TSGNE_OK;
-}
-
 }  // namespace
 }  // namespace tsgne
 
@@ -220,17 +223,23 @@ extern "C" {
 
 tsgne_status tsgne_batch_run(tsgne_graph* const* graphs, float* const* Y_d, const int32_t* n_iter, int32_t count,
                              const tsgne_params* p, void* stream) {
-  if (tsgne_status st = check_batch_args(graphs, Y_d, count, p)) return st;
+  if (tsgne_status st = check_batch_args(graphs, const_cast<const float* const*>(Y_d), count, p)) return st;
   if (!n_iter) return fail(TSGNE_E_INVAL, "n_iter is NULL");
-  for (int32_t k = 0; k < count; ++k)
+  int32_t max_iter = 0;
+  for (int32_t k = 0; k < count; ++k) {
     if (n_iter[k] < 0) return fail(TSGNE_E_INVAL, "n_iter must be >= 0");
+    max_iter = std::max(max_iter, n_iter[k]);
+  }
   DeviceGuard dg(graphs[0]->device);
   CaptureStream cs(stream);
   if (!cs.s) return fail(TSGNE_E_DEVICE, "cannot create a stream");
   const int32_t R = p->tile_rows ? p->tile_rows : default_batch_R(graphs, count);
+  PooledState ps;
+  std::vector<BatchMember> members;
+  if (tsgne_status st = ps.make(graphs, Y_d, n_iter, count, members, cs.s)) return st;
   BatchRun br;
-  if (tsgne_status st = br.setup(graphs, Y_d, n_iter, count, R, p, cs.s)) return st;
-  if (tsgne_status st = run_captured(br, p, br.max_iter, cs.s)) return st;
+  if (tsgne_status st = br.setup(members.data(), count, R, p)) return st;
+  if (tsgne_status st = run_batch_steps(br, p, max_iter, kCaptureSteps, cs.s)) return st;
   uint32_t* flag = nullptr;
   TSGNE_HIP(dalloc(&flag, 1), "allocate flag");
   struct F {
@@ -251,22 +260,21 @@ tsgne_status tsgne_batch_run(tsgne_graph* const* graphs, float* const* Y_d, cons
 tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d, int32_t count,
                             const tsgne_params* p, int32_t steps, int32_t* best_tile_rows, double* ms_per_step,
                             void* stream) {
-  if (!Y_d || !best_tile_rows) return fail(TSGNE_E_INVAL, "null pointer");
+  if (!best_tile_rows) return fail(TSGNE_E_INVAL, "null pointer");
   if (steps < 1) return fail(TSGNE_E_INVAL, "steps must be >= 1");
-  std::vector<float*> scratch((size_t)std::max(count, 0), nullptr);
-  if (tsgne_status st = check_batch_args(graphs, const_cast<float* const*>(Y_d), count, p)) return st;
+  if (tsgne_status st = check_batch_args(graphs, Y_d, count, p)) return st;
   DeviceGuard dg(graphs[0]->device);
   CaptureStream cs(stream);
   if (!cs.s) return fail(TSGNE_E_DEVICE, "cannot create a stream");
+  std::vector<float*> scratch((size_t)count, nullptr);
   struct Scratch {
     std::vector<float*>& v;
     ~Scratch() {
       for (float*& q : v) dfree(q);
     }
   } sc{scratch};
-  for (int32_t k = 0; k < count; ++k) {
+  for (int32_t k = 0; k < count; ++k)
     TSGNE_HIP(dalloc(&scratch[(size_t)k], 2 * (size_t)graphs[k]->n), "allocate scratch layout");
-  }
   std::vector<int32_t> iters((size_t)count, steps + 1);
   const int32_t candidates[3] = {4, 8, 16};
   double best = INFINITY;
@@ -287,11 +295,14 @@ tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d,
       TSGNE_HIP(hipMemcpyAsync(scratch[(size_t)k], Y_d[k], sizeof(float) * 2 * graphs[k]->n,
                                hipMemcpyDeviceToDevice, cs.s),
                 "copy layout");
+    PooledState ps;
+    std::vector<BatchMember> members;
+    if (tsgne_status st = ps.make(graphs, scratch.data(), iters.data(), count, members, cs.s)) return st;
     BatchRun br;
-    if (tsgne_status st = br.setup(graphs, scratch.data(), iters.data(), count, R, p, cs.s)) return st;
-    TSGNE_HIP(launch_batch_step(br.bp, *p, cs.s), "warm-up step");
+    if (tsgne_status st = br.setup(members.data(), count, R, p)) return st;
+    TSGNE_HIP(launch_batch_step(br.plan(), *p, cs.s), "warm-up step");
     TSGNE_HIP(hipEventRecord(e0, cs.s), "record event");
-    for (int32_t k = 0; k < steps; ++k) TSGNE_HIP(launch_batch_step(br.bp, *p, cs.s), "timed step");
+    for (int32_t k = 0; k < steps; ++k) TSGNE_HIP(launch_batch_step(br.plan(), *p, cs.s), "timed step");
     TSGNE_HIP(hipEventRecord(e1, cs.s), "record event");
     TSGNE_HIP(hipEventSynchronize(e1), "synchronise autotune");
     float ms = 0.f;

@@ -64,6 +64,8 @@ struct BatchDesc {
   float* zpart32;
   double* Z;
   double2* attract;
+  int32_t* t;        // this graph's step index (advanced after every step)
+  const int32_t* limit;  // steps run only while t < limit (a round's allotment)
   int64_t n_items;
   int32_t n;
   int32_t nb;
@@ -78,7 +80,6 @@ struct BatchPlan {
   int2* light_chunks = nullptr;   // (graph, first row) per 32-row block
   int2* heavy = nullptr;          // (graph, row) per heavy row
   int2* row_blocks = nullptr;     // (graph, first row) per 256-row block
-  int32_t* t = nullptr;           // step index
   int64_t n_items = 0;
   int32_t n_light_chunks = 0;
   int32_t n_heavy = 0;
@@ -87,6 +88,34 @@ struct BatchPlan {
   int32_t R = 0;
   int32_t T = 0;
 };
+
+// One graph of a batch with its own optimiser state (device pointers).
+struct BatchMember {
+  tsgne_graph* g;
+  float* Y;        // float32[n][2]
+  float* U;        // float32[n][2]
+  float* G;        // float32[n][2] gains
+  int32_t* t;      // step index
+  const int32_t* limit;  // step index at which this graph pauses (device int)
+  int32_t n_iter;
+};
+
+// Launch tables for a set of members, all tiled with the same R.
+class BatchRun {
+ public:
+  ~BatchRun();
+  tsgne_status setup(const BatchMember* m, int32_t count, int32_t R, const tsgne_params* p);
+  const BatchPlan& plan() const { return bp_; }
+
+ private:
+  BatchPlan bp_;
+  void* tables_ = nullptr;
+};
+
+// Runs n_steps batched steps: one captured sequence of up to `chunk` steps,
+// replayed (graphs past their n_iter skip their work).  Synchronises s.
+tsgne_status run_batch_steps(const BatchRun& br, const tsgne_params* p, int32_t n_steps, int32_t chunk,
+                             hipStream_t s);
 
 // Event-pair timing of kernel phases (see tsgne_graph_set_timing).
 struct PhaseTimer {

@@ -1,0 +1,553 @@
+// Layout server: continuous batching of t-SGNE requests on one GPU.
+//
+// Requests are copied in at submission and queued.  A worker thread owns all
+// device work: between rounds it admits queued requests while their estimated
+// device footprint fits the budget (building their affinities), then advances
+// every active request by `steps_per_round` steps in one captured batched
+// sequence (each request at its own step index), and completes the requests
+// that reached n_iter (layout copied out, memory released).  Every request's
+// arithmetic and reduction order depend only on itself and the server's tile
+// size, so its layout is the same alone or in any mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace tsgne {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double seconds_since(Clock::time_point t0, Clock::time_point t) {
+  return std::chrono::duration<double>(t - t0).count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t n = 0, d = 0, n_iter = 0;
+  float perplexity = 30.f;
+  std::vector<int32_t> edges;
+  std::vector<float> X, Y0, Y;
+  size_t footprint = 0;
+  Clock::time_point t_submit, t_done;
+  bool done = false, cancel = false;
+  tsgne_status status = TSGNE_OK;
+  std::string error;
+};
+
+struct Slot {
+  std::shared_ptr<Request> req;
+  tsgne_graph* g = nullptr;
+  float* state = nullptr;  // Y, U, gains: float32[3][n][2]
+  int32_t* t = nullptr;
+  int32_t progress = 0;    // steps already run (host view)
+};
+
+// Device bytes a request holds while active (graph, workspace, state) plus the
+// transient build buffers, for tile rows R.
+size_t footprint_bytes(int32_t n, int64_t m, int32_t d, int32_t R) {
+  const int64_t nnz = 2 * m;
+  const int64_t T = (int64_t)kWave * R, nb = (n + T - 1) / T;
+  const int64_t items = nb * (nb + 1) / 2;
+  const int64_t graph = 4 * (n + 1) + 16 * nnz + 8 * (int64_t)n + 4 * (int64_t)n;
+  const int64_t work = 8 * nb * nb * T + 12 * items + 16 * (int64_t)n + 8 * 1024 + 4096;
+  const int64_t state = 24 * (int64_t)n + 4;
+  const int64_t build = 4 * (int64_t)n * d + 16 * nnz + 4 * (n + 1) + 4 * nnz;
+  return (size_t)(graph + work + state + build);
+}
+
+}  // namespace
+}  // namespace tsgne
+
+using namespace tsgne;
+
+struct tsgne_server {
+  tsgne_server_config cfg{};
+  int device = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<uint64_t, std::shared_ptr<Request>> all;
+  std::vector<Slot> active;
+  bool stop = false;
+  int32_t n_active = 0;  // active.size(), published under mu for other threads
+  uint64_t next_ticket = 1;
+  size_t hbm_used = 0;
+  // statistics
+  int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, rounds = 0;
+  std::vector<double> latencies_ms;
+  bool have_first = false;
+  Clock::time_point t_first, t_last_done;
+  double busy_s = 0.0;
+
+  void run();
+  void admit(hipStream_t s);
+  void finish(Slot& sl, tsgne_status st, const std::string& why, bool copy_out, hipStream_t s);
+};
+
+namespace {
+
+void free_slot(Slot& sl) {
+  if (sl.g) tsgne_graph_free(sl.g);
+  dfree(sl.state);
+  dfree(sl.t);
+  sl.g = nullptr;
+}
+
+// Uploads one request and builds its graph; on failure frees what it made.
+tsgne_status build_slot(const Request& r, int32_t R, hipStream_t s, Slot& out) {
+  std::vector<int32_t> rp((size_t)r.n + 1), col(std::max<size_t>(r.edges.size(), 1));
+  int64_t nnz = 0;
+  if (tsgne_status st = tsgne_csr_from_edges(r.n, (int64_t)r.edges.size() / 2, r.edges.data(), rp.data(),
+                                             col.data(), &nnz))
+    return st;
+  int32_t* d_rp = nullptr;
+  int32_t* d_col = nullptr;
+  float* d_X = nullptr;
+  struct Tmp {
+    int32_t*& a;
+    int32_t*& b;
+    float*& c;
+    ~Tmp() {
+      dfree(a);
+      dfree(b);
+      dfree(c);
+    }
+  } tmp{d_rp, d_col, d_X};
+  TSGNE_HIP(dalloc(&d_rp, rp.size()), "allocate request CSR");
+  TSGNE_HIP(dalloc(&d_col, (size_t)std::max<int64_t>(nnz, 1)), "allocate request CSR");
+  TSGNE_HIP(dalloc(&d_X, (size_t)r.n * r.d), "allocate request embedding");
+  TSGNE_HIP(hipMemcpyAsync(d_rp, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice, s), "upload CSR");
+  if (nnz) TSGNE_HIP(hipMemcpyAsync(d_col, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s), "upload CSR");
+  TSGNE_HIP(hipMemcpyAsync(d_X, r.X.data(), sizeof(float) * r.X.size(), hipMemcpyHostToDevice, s), "upload X");
+  tsgne_graph* g = nullptr;
+  if (tsgne_status st = tsgne_build_P(r.n, nnz, d_rp, d_col, d_X, r.d, r.perplexity, s, &g)) return st;
+  out.g = g;
+  const size_t len = 2 * (size_t)r.n;
+  std::vector<float> init(3 * len, 0.0f);
+  std::copy(r.Y0.begin(), r.Y0.end(), init.begin());
+  std::fill(init.begin() + 2 * len, init.end(), 1.0f);
+  const int32_t zero = 0;
+  hipError_t e = dalloc(&out.state, 3 * len);
+  if (e == hipSuccess) e = dalloc(&out.t, 1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out.state, init.data(), sizeof(float) * init.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out.t, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_slot(out);
+    return hip_fail(e, "set up request state");
+  }
+  tsgne_params pr{};
+  tsgne_params_default(&pr);
+  pr.tile_rows = R;
+  pr.repulsion = TSGNE_REPULSION_SYMMETRIC;
+  if (tsgne_status st = ensure_workspace(g, &pr)) {
+    free_slot(out);
+    return st;
+  }
+  return TSGNE_OK;
+}
+
+}  // namespace
+
+void tsgne_server::finish(Slot& sl, tsgne_status st, const std::string& why, bool copy_out, hipStream_t s) {
+  Request& r = *sl.req;
+  if (copy_out) {
+    r.Y.resize(2 * (size_t)r.n);
+    hipError_t e = hipMemcpyAsync(r.Y.data(), sl.state, sizeof(float) * r.Y.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      st = TSGNE_E_DEVICE;
+    } else {
+      for (float v : r.Y)
+        if (!std::isfinite(v)) {
+          st = TSGNE_E_NONFINITE;
+          break;
+        }
+    }
+  }
+  free_slot(sl);
+  std::lock_guard<std::mutex> lk(mu);
+  hbm_used -= r.footprint;
+  r.t_done = Clock::now();
+  r.status = st;
+  r.error = why;
+  r.done = true;
+  if (st == TSGNE_OK) {
+    ++completed;
+    latencies_ms.push_back(1e3 * seconds_since(r.t_submit, r.t_done));
+    t_last_done = r.t_done;
+  } else if (r.cancel) {
+    ++cancelled;
+  } else {
+    ++failed;
+  }
+  cv_done.notify_all();
+}
+
+void tsgne_server::admit(hipStream_t s) {
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (queue.empty() || (int32_t)active.size() >= cfg.max_active) return;  // only this thread changes active
+      if (hbm_used + queue.front()->footprint > (size_t)cfg.hbm_budget) return;  // wait for memory
+      r = queue.front();
+      queue.pop_front();
+      hbm_used += r->footprint;
+    }
+    Slot sl;
+    sl.req = r;
+    tsgne_status st = build_slot(*r, cfg.tile_rows, s, sl);
+    if (st != TSGNE_OK) {
+      finish(sl, st, tsgne_last_error(), false, s);
+      continue;
+    }
+    active.push_back(sl);
+  }
+}
+
+void tsgne_server::run() {
+  (void)hipSetDevice(device);
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  int32_t* limits = nullptr;  // per-member pause step of the current round
+  if (dalloc(&limits, (size_t)cfg.max_active) != hipSuccess) limits = nullptr;
+  BatchRun br;
+  bool plan_valid = false;
+  std::map<int32_t, hipGraphExec_t> execs;  // captured rounds by length, for the current membership
+  auto drop_execs = [&]() {
+    for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
+    execs.clear();
+    plan_valid = false;
+  };
+  // ordered pairs evaluated per second, refined from measured rounds
+  double pair_rate = 5e12;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      if (stop) break;
+    }
+    const size_t before = active.size();
+    admit(s);
+    // cancelled active requests leave at a round boundary
+    bool changed = active.size() != before;
+    for (size_t k = 0; k < active.size();) {
+      bool c;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        c = active[k].req->cancel;
+      }
+      if (c) {
+        finish(active[k], TSGNE_E_CANCELLED, "cancelled", false, s);
+        active.erase(active.begin() + (long)k);
+        changed = true;
+      } else {
+        ++k;
+      }
+    }
+    if (changed) drop_execs();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      n_active = (int32_t)active.size();
+    }
+    if (active.empty()) continue;
+    const Clock::time_point t0 = Clock::now();
+    tsgne_status st = limits ? TSGNE_OK : fail(TSGNE_E_NOMEM, "allocate round limits");
+    if (st == TSGNE_OK && !plan_valid) {
+      std::vector<BatchMember> m;
+      for (size_t k = 0; k < active.size(); ++k) {
+        Slot& sl = active[k];
+        const size_t len = 2 * (size_t)sl.req->n;
+        m.push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t, limits + k,
+                                sl.req->n_iter});
+      }
+      st = br.setup(m.data(), (int32_t)m.size(), cfg.tile_rows, &cfg.params);
+      if (st == TSGNE_OK) plan_valid = true;
+    }
+    // Steps per request this round: an equal share of the round's target time
+    // (small graphs take many steps, large ones few), or the same count for
+    // all when no target is set.
+    std::vector<int32_t> take(active.size()), lim(active.size());
+    int32_t longest = 1;
+    double pairs = 0.0;
+    const double share = cfg.round_ms > 0.f ? pair_rate * 1e-3 * cfg.round_ms / (double)active.size() : 0.0;
+    for (size_t k = 0; k < active.size(); ++k) {
+      const Slot& sl = active[k];
+      const double per_step = (double)sl.req->n * (double)(sl.req->n - 1) + 1.0;
+      int32_t steps = cfg.steps_per_round;
+      if (share > 0.0) steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
+      steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
+      take[k] = steps;
+      lim[k] = sl.progress + steps;
+      longest = std::max(longest, steps);
+      pairs += per_step * steps;
+    }
+    int32_t len = 1;
+    while (len < longest) len *= 2;
+    len = std::min(len, cfg.steps_per_round);
+    if (st == TSGNE_OK) {
+      hipError_t e = hipMemcpyAsync(limits, lim.data(), sizeof(int32_t) * lim.size(), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) st = hip_fail(e, "upload round limits");
+    }
+    if (st == TSGNE_OK && !execs.count(len)) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      hipError_t le = hipSuccess;
+      for (int32_t k = 0; e == hipSuccess && k < len && le == hipSuccess; ++k)
+        le = launch_batch_step(br.plan(), cfg.params, s);
+      if (e == hipSuccess) e = hipStreamEndCapture(s, &graph);
+      if (e == hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) st = hip_fail(e, "capture a serving round");
+      else execs[len] = exec;
+    }
+    if (st == TSGNE_OK) {
+      hipError_t e = hipGraphLaunch(execs[len], s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = hip_fail(e, "run a serving round");
+    }
+    if (st != TSGNE_OK) {
+      // a device failure ends every active request with that status
+      const std::string why = tsgne_last_error();
+      for (Slot& sl : active) finish(sl, st, why, false, s);
+      active.clear();
+      drop_execs();
+      continue;
+    }
+    const double dt = seconds_since(t0, Clock::now());
+    if (dt > 0.0 && pairs > 1e9) pair_rate = 0.5 * pair_rate + 0.5 * pairs / dt;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      ++rounds;
+      busy_s += dt;
+    }
+    bool left = false;
+    for (size_t k = 0, j = 0; k < active.size(); ++j) {
+      Slot& sl = active[k];
+      sl.progress += take[j];
+      if (sl.progress >= sl.req->n_iter) {
+        finish(sl, TSGNE_OK, "", true, s);
+        active.erase(active.begin() + (long)k);
+        left = true;
+      } else {
+        ++k;
+      }
+    }
+    if (left) drop_execs();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      n_active = (int32_t)active.size();
+    }
+  }
+  drop_execs();
+  for (Slot& sl : active) {
+    sl.req->cancel = true;
+    finish(sl, TSGNE_E_CANCELLED, "server destroyed", false, s);
+  }
+  active.clear();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& r : queue) {
+      r->cancel = true;
+      r->done = true;
+      r->status = TSGNE_E_CANCELLED;
+      ++cancelled;
+    }
+    queue.clear();
+    n_active = 0;
+    cv_done.notify_all();
+  }
+  dfree(limits);
+  if (s) (void)hipStreamDestroy(s);
+}
+
+extern "C" {
+
+void tsgne_server_config_default(tsgne_server_config* c) {
+  if (!c) return;
+  c->hbm_budget = 0;
+  c->max_active = 64;
+  c->max_queue = 1 << 20;
+  c->steps_per_round = 64;
+  c->round_ms = 25.0f;
+  c->tile_rows = 8;
+  tsgne_params_default(&c->params);
+}
+
+tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** out) {
+  if (!cfg || !out) return fail(TSGNE_E_INVAL, "null pointer");
+  *out = nullptr;
+  if (tsgne_status st = validate_params(&cfg->params)) return st;
+  if (!std::isfinite(cfg->round_ms)) return fail(TSGNE_E_INVAL, "round_ms must be finite");
+  if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
+    return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
+  if (cfg->tile_rows != 4 && cfg->tile_rows != 8 && cfg->tile_rows != 16)
+    return fail(TSGNE_E_INVAL, "tile_rows must be 4, 8 or 16");
+  if (cfg->hbm_budget < 0) return fail(TSGNE_E_INVAL, "hbm_budget must be >= 0");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TSGNE_E_DEVICE, "no HIP device");
+  tsgne_server* srv = new (std::nothrow) tsgne_server();
+  if (!srv) return fail(TSGNE_E_NOMEM, "host allocation failed");
+  srv->cfg = *cfg;
+  srv->device = dev;
+  if (srv->cfg.hbm_budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      delete srv;
+      return fail(TSGNE_E_DEVICE, "cannot query device memory");
+    }
+    srv->cfg.hbm_budget = (int64_t)(0.8 * (double)free_b);
+  }
+  srv->worker = std::thread([srv] { srv->run(); });
+  *out = srv;
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uint64_t* ticket) {
+  if (!srv || !rq || !ticket) return fail(TSGNE_E_INVAL, "null pointer");
+  if (rq->n < 1 || rq->m < 0 || rq->d < 1 || rq->n_iter < 0) return fail(TSGNE_E_INVAL, "bad request sizes");
+  if (!std::isfinite(rq->perplexity) || rq->perplexity <= 1.0f) return fail(TSGNE_E_INVAL, "perplexity must be > 1");
+  if (!rq->X_h || !rq->Y0_h || (rq->m > 0 && !rq->edges_h)) return fail(TSGNE_E_INVAL, "null request buffer");
+  auto r = std::make_shared<Request>();
+  r->n = rq->n;
+  r->d = rq->d;
+  r->n_iter = rq->n_iter;
+  r->perplexity = rq->perplexity;
+  r->footprint = footprint_bytes(rq->n, rq->m, rq->d, srv->cfg.tile_rows);
+  if (r->footprint > (size_t)srv->cfg.hbm_budget)
+    return fail(TSGNE_E_NOMEM, "request needs more device memory than the server's budget");
+  r->edges.assign(rq->edges_h, rq->edges_h + 2 * rq->m);
+  r->X.assign(rq->X_h, rq->X_h + (size_t)rq->n * rq->d);
+  r->Y0.assign(rq->Y0_h, rq->Y0_h + 2 * (size_t)rq->n);
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if ((int64_t)srv->queue.size() >= srv->cfg.max_queue) return fail(TSGNE_E_BUSY, "request queue is full");
+  r->ticket = srv->next_ticket++;
+  r->t_submit = Clock::now();
+  if (!srv->have_first) {
+    srv->have_first = true;
+    srv->t_first = r->t_submit;
+  }
+  srv->queue.push_back(r);
+  srv->all[r->ticket] = r;
+  ++srv->submitted;
+  *ticket = r->ticket;
+  srv->cv_work.notify_one();
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_poll(tsgne_server* srv, uint64_t ticket, float* Y_h, int32_t* done, tsgne_status* result) {
+  if (!srv || !done) return fail(TSGNE_E_INVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  Request& r = *it->second;
+  *done = r.done ? 1 : 0;
+  if (r.done) {
+    if (result) *result = r.status;
+    if (Y_h && r.status == TSGNE_OK) std::copy(r.Y.begin(), r.Y.end(), Y_h);
+  }
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_wait(tsgne_server* srv, uint64_t ticket, float* Y_h, tsgne_status* result) {
+  if (!srv) return fail(TSGNE_E_INVAL, "null pointer");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  srv->cv_done.wait(lk, [&] { return r->done; });
+  if (result) *result = r->status;
+  if (Y_h && r->status == TSGNE_OK) std::copy(r->Y.begin(), r->Y.end(), Y_h);
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_release(tsgne_server* srv, uint64_t ticket) {
+  if (!srv) return fail(TSGNE_E_INVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  if (!it->second->done) return fail(TSGNE_E_BUSY, "request still running");
+  srv->all.erase(it);
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_cancel(tsgne_server* srv, uint64_t ticket) {
+  if (!srv) return fail(TSGNE_E_INVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  Request& r = *it->second;
+  if (r.done) return TSGNE_OK;
+  r.cancel = true;
+  for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q) {
+    if ((*q)->ticket == ticket) {
+      srv->queue.erase(q);
+      r.done = true;
+      r.status = TSGNE_E_CANCELLED;
+      r.t_done = Clock::now();
+      ++srv->cancelled;
+      srv->cv_done.notify_all();
+      break;
+    }
+  }
+  srv->cv_work.notify_one();
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_get_stats(tsgne_server* srv, tsgne_server_stats* out) {
+  if (!srv || !out) return fail(TSGNE_E_INVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  out->submitted = srv->submitted;
+  out->completed = srv->completed;
+  out->failed = srv->failed;
+  out->cancelled = srv->cancelled;
+  out->queued = (int32_t)srv->queue.size();
+  out->active = srv->n_active;
+  out->hbm_in_use = (int64_t)srv->hbm_used;
+  out->hbm_budget = srv->cfg.hbm_budget;
+  out->rounds = srv->rounds;
+  out->busy_s = srv->busy_s;
+  std::vector<double> l = srv->latencies_ms;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double q) {
+    if (l.empty()) return 0.0;
+    const size_t k = (size_t)std::min<double>((double)l.size() - 1, std::ceil(q * (double)l.size()) - 1);
+    return l[k];
+  };
+  out->latency_p50_ms = pct(0.50);
+  out->latency_p99_ms = pct(0.99);
+  double sum = 0.0;
+  for (double v : l) sum += v;
+  out->latency_mean_ms = l.empty() ? 0.0 : sum / (double)l.size();
+  const double span = (srv->completed > 0) ? seconds_since(srv->t_first, srv->t_last_done) : 0.0;
+  out->layouts_per_s = span > 0.0 ? (double)srv->completed / span : 0.0;
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_destroy(tsgne_server* srv) {
+  if (!srv) return TSGNE_OK;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  if (srv->worker.joinable()) srv->worker.join();
+  delete srv;
+  return TSGNE_OK;
+}
+
+}  // extern "C"

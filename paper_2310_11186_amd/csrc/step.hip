@@ -477,24 +477,27 @@ __global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ pa
 // ---------------------------------------------------------------------------
 // Batched step over many graphs.  Every graph keeps its own tiling, item
 // order, partial buffers and reduction order, so a graph advanced inside a
-// batch computes exactly what it computes alone with the same tile size.  The
-// step index t lives in device memory (advanced by the last kernel of a step),
-// so one captured step can be replayed; graphs with t >= n_iter are skipped.
+// batch computes exactly what it computes alone with the same tile size.  Each
+// graph's step index lives in device memory (advanced by the last kernel of a
+// step), so a captured step can be replayed and graphs at different progress
+// can share a launch; graphs with t >= n_iter are skipped.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool batch_live(const BatchDesc& d, int32_t t) { return t < d.n_iter; }
+__device__ __forceinline__ bool batch_live(const BatchDesc& d) {
+  const int32_t t = *d.t;
+  return t < d.n_iter && t < *d.limit;
+}
 
 template <int R, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_batch_repulse(const BatchDesc* __restrict__ descs,
-                                                          const int4* __restrict__ items, int64_t n_items,
-                                                          const int32_t* __restrict__ tp) {
+                                                          const int4* __restrict__ items, int64_t n_items) {
   const int64_t item =
       (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (item >= n_items) return;
   const int4 it = items[item];
   const int32_t gi = __builtin_amdgcn_readfirstlane(it.x);
   const BatchDesc& d = descs[gi];
-  if (!batch_live(d, *tp)) return;
+  if (!batch_live(d)) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int32_t a = __builtin_amdgcn_readfirstlane(it.y), b = __builtin_amdgcn_readfirstlane(it.z);
   const int64_t li = __builtin_amdgcn_readfirstlane(it.w);
@@ -503,21 +506,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_repulse(const BatchDesc* __res
 }
 
 template <bool SPLIT>
-__global__ __launch_bounds__(kZThreads) void k_batch_zsum(const BatchDesc* __restrict__ descs,
-                                                          const int32_t* __restrict__ tp) {
+__global__ __launch_bounds__(kZThreads) void k_batch_zsum(const BatchDesc* __restrict__ descs) {
   const BatchDesc& d = descs[blockIdx.x];
-  if (!batch_live(d, *tp)) return;
+  if (!batch_live(d)) return;
   zsum_block<SPLIT>(d.zpart, d.zpart32, d.n_items, d.Z);
 }
 
 // One block of 256 threads covers 32 light rows of one graph (8 lanes each).
 template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_batch_attract_light(const BatchDesc* __restrict__ descs,
-                                                                const int2* __restrict__ chunks,
-                                                                const int32_t* __restrict__ tp) {
+                                                                const int2* __restrict__ chunks) {
   const int2 ch = chunks[blockIdx.x];
   const BatchDesc& d = descs[ch.x];
-  if (!batch_live(d, *tp)) return;
+  if (!batch_live(d)) return;
   const int32_t i0 = ch.y + (int32_t)(threadIdx.x / kRowLanes);
   const int32_t i = min(i0, d.n - 1);
   const bool live = i0 < d.n && (d.row_ptr[i + 1] - d.row_ptr[i]) <= kHeavyDegree;
@@ -527,26 +528,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_attract_light(const BatchDesc*
 
 template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_batch_attract_heavy(const BatchDesc* __restrict__ descs,
-                                                                const int2* __restrict__ heavy, int32_t n_heavy,
-                                                                const int32_t* __restrict__ tp) {
+                                                                const int2* __restrict__ heavy, int32_t n_heavy) {
   const int32_t w = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
   if (w >= n_heavy) return;
   const int2 hr = heavy[w];
   const BatchDesc& d = descs[hr.x];
-  if (!batch_live(d, *tp)) return;
+  if (!batch_live(d)) return;
   attract_row<kWave, SPLIT>(d.row_ptr, d.col, d.P, d.Y, hr.y, (int)(threadIdx.x & (kWave - 1)), d.attract);
 }
 
 // One block of 256 threads covers 256 rows of one graph.
 template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchDesc* __restrict__ descs,
-                                                         const int2* __restrict__ blocks, const int32_t* __restrict__ tp,
-                                                         int32_t T, float ee, int32_t t_ee, float m_early, float m_late,
-                                                         float min_gain) {
+                                                         const int2* __restrict__ blocks, int32_t T, float ee,
+                                                         int32_t t_ee, float m_early, float m_late, float min_gain) {
   const int2 bl = blocks[blockIdx.x];
   const BatchDesc& d = descs[bl.x];
-  const int32_t t = *tp;
-  if (!batch_live(d, t)) return;
+  if (!batch_live(d)) return;
+  const int32_t t = *d.t;
   const int32_t i = bl.y + (int32_t)threadIdx.x;
   if (i >= d.n) return;
   const bool early = t < t_ee;
@@ -554,8 +553,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchDesc* __rest
                     d.eta, min_gain, true, nullptr);
 }
 
-__global__ void k_batch_advance(int32_t* __restrict__ tp) {
-  if (threadIdx.x == 0) *tp += 1;
+__global__ __launch_bounds__(kBlock) void k_batch_advance(const BatchDesc* __restrict__ descs, int32_t count) {
+  const int32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g < count && batch_live(descs[g])) *descs[g].t += 1;
 }
 
 // KL = sum_e P_e log(P_e / q_e), q_e = w_e / Z, in FP64: fixed grid, strided
@@ -700,9 +700,9 @@ template <int R>
 hipError_t launch_batch_repulse_r(const BatchPlan& bp, bool split, hipStream_t s) {
   const dim3 grid((unsigned)((bp.n_items + kWavesPerBlock - 1) / kWavesPerBlock));
   if (split)
-    hipLaunchKernelGGL((k_batch_repulse<R, true>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items, bp.t);
+    hipLaunchKernelGGL((k_batch_repulse<R, true>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items);
   else
-    hipLaunchKernelGGL((k_batch_repulse<R, false>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items, bp.t);
+    hipLaunchKernelGGL((k_batch_repulse<R, false>), grid, dim3(kBlock), 0, s, bp.descs, bp.items, bp.n_items);
   return hipGetLastError();
 }
 
@@ -718,38 +718,35 @@ hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStre
     }
     if (e != hipSuccess) return e;
   }
-  if (split) hipLaunchKernelGGL(k_batch_zsum<true>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs, bp.t);
-  else hipLaunchKernelGGL(k_batch_zsum<false>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs, bp.t);
+  if (split) hipLaunchKernelGGL(k_batch_zsum<true>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs);
+  else hipLaunchKernelGGL(k_batch_zsum<false>, dim3(bp.count), dim3(kZThreads), 0, s, bp.descs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (bp.n_light_chunks > 0) {
     if (split)
       hipLaunchKernelGGL(k_batch_attract_light<true>, dim3(bp.n_light_chunks), dim3(kBlock), 0, s, bp.descs,
-                         bp.light_chunks, bp.t);
+                         bp.light_chunks);
     else
       hipLaunchKernelGGL(k_batch_attract_light<false>, dim3(bp.n_light_chunks), dim3(kBlock), 0, s, bp.descs,
-                         bp.light_chunks, bp.t);
+                         bp.light_chunks);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (bp.n_heavy > 0) {
     const unsigned hb = blocks_for(bp.n_heavy, kWavesPerBlock);
     if (split)
-      hipLaunchKernelGGL(k_batch_attract_heavy<true>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy,
-                         bp.t);
+      hipLaunchKernelGGL(k_batch_attract_heavy<true>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy);
     else
-      hipLaunchKernelGGL(k_batch_attract_heavy<false>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy,
-                         bp.t);
+      hipLaunchKernelGGL(k_batch_attract_heavy<false>, dim3(hb), dim3(kBlock), 0, s, bp.descs, bp.heavy, bp.n_heavy);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (split)
-    hipLaunchKernelGGL(k_batch_update<true>, dim3(bp.n_row_blocks), dim3(kBlock), 0, s, bp.descs, bp.row_blocks, bp.t,
-                       bp.T, p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late,
-                       p.min_gain);
+    hipLaunchKernelGGL(k_batch_update<true>, dim3(bp.n_row_blocks), dim3(kBlock), 0, s, bp.descs, bp.row_blocks, bp.T,
+                       p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late, p.min_gain);
   else
     hipLaunchKernelGGL(k_batch_update<false>, dim3(bp.n_row_blocks), dim3(kBlock), 0, s, bp.descs, bp.row_blocks,
-                       bp.t, bp.T, p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late,
+                       bp.T, p.early_exaggeration, p.exaggeration_iters, p.momentum_early, p.momentum_late,
                        p.min_gain);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, bp.t);
+  hipLaunchKernelGGL(k_batch_advance, dim3(blocks_for(bp.count, kBlock)), dim3(kBlock), 0, s, bp.descs, bp.count);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ TSGNE_E_NOMEM = -3
 TSGNE_E_DEVICE = -4
 TSGNE_E_NONFINITE = -5
 TSGNE_E_BUSY = -6
+TSGNE_E_CANCELLED = -7
 
 TSGNE_PREC_SPLIT = 0
 TSGNE_PREC_FP32 = 1
@@ -36,6 +37,9 @@ EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
+    "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
+    "tsgne_server_wait", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
+    "tsgne_server_destroy",
 )
 
 TSGNE_PHASES = ("repulsion", "zsum", "attract", "update", "kl")
@@ -64,6 +68,41 @@ class tsgne_params(ctypes.Structure):
 
 class tsgne_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
+
+
+class tsgne_server_config(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_int64),
+        ("max_active", ctypes.c_int32),
+        ("max_queue", ctypes.c_int32),
+        ("steps_per_round", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
+        ("params", tsgne_params),
+        ("round_ms", ctypes.c_float),
+    ]
+
+
+class tsgne_request(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("edges_h", ctypes.c_void_p),
+        ("d", ctypes.c_int32),
+        ("X_h", ctypes.c_void_p),
+        ("Y0_h", ctypes.c_void_p),
+        ("perplexity", ctypes.c_float),
+        ("n_iter", ctypes.c_int32),
+    ]
+
+
+class tsgne_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64), ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
+        ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64), ("rounds", ctypes.c_int64),
+        ("busy_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+        ("latency_mean_ms", ctypes.c_double), ("layouts_per_s", ctypes.c_double),
+    ]
 
 
 _lib = None
@@ -95,6 +134,15 @@ def lib():
             "tsgne_batch_run": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32), i32, P, vp]),
             "tsgne_autotune": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_server_config_default": (None, [ctypes.POINTER(tsgne_server_config)]),
+            "tsgne_server_create": (st, [ctypes.POINTER(tsgne_server_config), ctypes.POINTER(vp)]),
+            "tsgne_server_submit": (st, [vp, ctypes.POINTER(tsgne_request), ctypes.POINTER(ctypes.c_uint64)]),
+            "tsgne_server_poll": (st, [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "tsgne_server_wait": (st, [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32)]),
+            "tsgne_server_release": (st, [vp, ctypes.c_uint64]),
+            "tsgne_server_cancel": (st, [vp, ctypes.c_uint64]),
+            "tsgne_server_get_stats": (st, [vp, ctypes.POINTER(tsgne_server_stats)]),
+            "tsgne_server_destroy": (st, [vp]),
             "tsgne_graph_set_timing": (st, [vp, i32]),
             "tsgne_graph_timing": (st, [vp, ctypes.POINTER(tsgne_timing)]),
         }
@@ -309,3 +357,79 @@ def tsgne_autotune(graphs, Ys, params: tsgne_params, steps: int = 3, stream=None
     _check(lib().tsgne_autotune(hs, ys, count, ctypes.byref(params), int(steps), ctypes.byref(best), ms,
                                 _stream(stream)))
     return best.value, list(ms)
+
+
+class Server:
+    """Continuous-batching layout server (tsgne_server_*).  Requests are host
+    numpy arrays; the server copies them in at submission."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
+                 steps_per_round: int = 64, tile_rows: int = 8, params: tsgne_params | None = None,
+                 round_ms: float = 25.0):
+        cfg = tsgne_server_config()
+        lib().tsgne_server_config_default(ctypes.byref(cfg))
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_active = int(max_active)
+        cfg.max_queue = int(max_queue)
+        cfg.steps_per_round = int(steps_per_round)
+        cfg.tile_rows = int(tile_rows)
+        cfg.round_ms = float(round_ms)
+        if params is not None:
+            cfg.params = params
+        h = ctypes.c_void_p(None)
+        _check(lib().tsgne_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h.value
+        self._n = {}
+
+    def submit(self, n: int, edges, X, Y0, perplexity: float = 30.0, n_iter: int = 500) -> int:
+        e = np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2))
+        X = np.ascontiguousarray(X, np.float32)
+        Y0 = np.ascontiguousarray(Y0, np.float32)
+        if X.shape[0] != n or Y0.shape != (n, 2):
+            raise ValueError("X must be [n, d] and Y0 [n, 2]")
+        rq = tsgne_request(n=n, m=e.shape[0], edges_h=e.ctypes.data if e.size else None, d=X.shape[1],
+                           X_h=X.ctypes.data, Y0_h=Y0.ctypes.data, perplexity=float(perplexity),
+                           n_iter=int(n_iter))
+        t = ctypes.c_uint64(0)
+        _check(lib().tsgne_server_submit(self._h, ctypes.byref(rq), ctypes.byref(t)))
+        self._n[t.value] = n
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, status, Y or None)."""
+        Y = np.zeros((self._n[ticket], 2), np.float32)
+        done, st = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().tsgne_server_poll(self._h, ticket, Y.ctypes.data, ctypes.byref(done), ctypes.byref(st)))
+        if not done.value:
+            return False, None, None
+        return True, st.value, (Y if st.value == TSGNE_OK else None)
+
+    def wait(self, ticket: int):
+        """(status, Y or None), blocking."""
+        Y = np.zeros((self._n[ticket], 2), np.float32)
+        st = ctypes.c_int32(0)
+        _check(lib().tsgne_server_wait(self._h, ticket, Y.ctypes.data, ctypes.byref(st)))
+        return st.value, (Y if st.value == TSGNE_OK else None)
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib().tsgne_server_cancel(self._h, ticket))
+
+    def release(self, ticket: int) -> None:
+        _check(lib().tsgne_server_release(self._h, ticket))
+        self._n.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = tsgne_server_stats()
+        _check(lib().tsgne_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in tsgne_server_stats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            lib().tsgne_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,103 @@
+"""The layout server (tsgne_server_*) through the C-ABI: a request's layout is
+the same alone and in the mix, admission by memory budget queues requests,
+and failures (non-finite input, cancellation, oversize, full queue) stay
+with the request that caused them."""
+import numpy as np
+import pytest
+
+from paper_2310_11186_amd import synth, tsgne
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = dict(exaggeration_iters=15, learning_rate=40.0)
+
+
+def alone(gi, n_iter, R, gpu):
+    import torch
+    rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
+    g = tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                            torch.from_numpy(gi.X).to(gpu), 30.0)
+    Y = torch.from_numpy(gi.Y0).to(gpu)
+    tsgne.tsgne_run(g, Y, n_iter, tsgne.tsgne_params_default(tile_rows=R, repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC,
+                                                             **PARAMS))
+    out = Y.cpu().numpy()
+    g.close()
+    return out
+
+
+def requests(seed):
+    sizes = [900, 300, 2100, 1300, 650, 1700, 400]
+    iters = [40, 13, 57, 30, 44, 25, 60]
+    gis = [synth.small_sbm(n, 3, 5.0, 8 + 4 * (k % 2), seed * 100 + k) for k, n in enumerate(sizes)]
+    return gis, iters
+
+
+@pytest.mark.parametrize("max_active,budget_scale,round_ms", [(3, 0, 25.0), (64, 1.3, 25.0), (64, 0, 0.0),
+                                                            (64, 0, 0.05)])
+def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms):
+    gis, iters = requests(1)
+    budget = 0
+    if budget_scale:
+        # room for about one large request at a time: admission waits for memory
+        R = 4
+        nb = (2100 + 64 * R - 1) // (64 * R)
+        budget = int(budget_scale * (8 * nb * nb * 64 * R + 2100 * 400 + 40 * 2100 * 6))
+    srv = tsgne.Server(hbm_budget=budget, max_active=max_active, steps_per_round=7, tile_rows=4,
+                       params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms)
+    tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(gis) and st["failed"] == 0
+    assert st["latency_p99_ms"] >= st["latency_p50_ms"] > 0 and st["layouts_per_s"] > 0
+    for gi, k, (status, Y) in zip(gis, iters, outs):
+        assert status == tsgne.TSGNE_OK
+        assert np.array_equal(Y, alone(gi, k, 4, gpu)), gi.n
+
+
+def test_failures_stay_with_their_request(gpu):
+    gis, iters = requests(2)
+    bad = synth.small_sbm(500, 2, 4.0, 8, 77)
+    Y0 = bad.Y0.copy()
+    Y0[17, 0] = np.nan
+    srv = tsgne.Server(max_active=8, steps_per_round=5, tile_rows=4, params=tsgne.tsgne_params_default(**PARAMS))
+    good = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis[:3], iters[:3])]
+    tb = srv.submit(bad.n, bad.edges, bad.X, Y0, 30.0, 20)
+    long_t = srv.submit(gis[3].n, gis[3].edges, gis[3].X, gis[3].Y0, 30.0, 10 ** 7)
+    srv.cancel(long_t)
+    status_bad, _ = srv.wait(tb)
+    status_long, _ = srv.wait(long_t)
+    assert status_bad == tsgne.TSGNE_E_NONFINITE
+    assert status_long == tsgne.TSGNE_E_CANCELLED
+    for gi, k, t in zip(gis[:3], iters[:3], good):
+        status, Y = srv.wait(t)
+        assert status == tsgne.TSGNE_OK
+        assert np.array_equal(Y, alone(gi, k, 4, gpu))
+    st = srv.stats()
+    assert st["failed"] == 1 and st["cancelled"] == 1 and st["completed"] == 3
+    srv.close()
+
+
+def test_oversize_and_full_queue(gpu):
+    gi = synth.small_sbm(3000, 3, 5.0, 8, 5)
+    srv = tsgne.Server(hbm_budget=1 << 20, max_active=1, max_queue=1, tile_rows=4)
+    with pytest.raises(tsgne.TsgneError) as e:
+        srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, 10)
+    assert e.value.status == tsgne.TSGNE_E_NOMEM
+    srv.close()
+    small = synth.small_sbm(200, 2, 4.0, 4, 6)
+    srv = tsgne.Server(max_active=1, max_queue=1, tile_rows=4, steps_per_round=5)
+    t0 = srv.submit(small.n, small.edges, small.X, small.Y0, 30.0, 10 ** 7)
+    busy = 0
+    extra = []
+    for _ in range(2):
+        try:
+            extra.append(srv.submit(small.n, small.edges, small.X, small.Y0, 30.0, 5))
+        except tsgne.TsgneError as err:
+            assert err.status == tsgne.TSGNE_E_BUSY
+            busy += 1
+    assert busy >= 1
+    srv.cancel(t0)
+    for t in extra:
+        srv.cancel(t)
+    srv.close()
