@@ -152,8 +152,8 @@ tsgne_status validate_params(const tsgne_params* p) {
   if (p->kl_every < 0) return fail(TSGNE_E_INVAL, "kl_every must be >= 0");
   if (p->repulsion < TSGNE_REPULSION_AUTO || p->repulsion > TSGNE_REPULSION_SYMMETRIC)
     return fail(TSGNE_E_INVAL, "unknown repulsion variant");
-  if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16)
-    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 4, 8 or 16");
+  if (p->tile_rows != 0 && !tile_rows_supported(p->tile_rows))
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 4, 8, 12, 14, 15 or 16");
   return TSGNE_OK;
 }
 

@@ -215,6 +215,11 @@ hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s);
 hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStream_t s);
 
+// Rows per lane for which the repulsion kernels are compiled.
+inline bool tile_rows_supported(int32_t R) {
+  return R == 4 || R == 8 || R == 12 || R == 14 || R == 15 || R == 16;
+}
+
 // Repulsion plan for n positions (R = 0 picks automatically).
 RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant);
 

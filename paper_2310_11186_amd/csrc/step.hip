@@ -86,7 +86,7 @@ __device__ __forceinline__ void sym_pass(const float (&yix)[R], const float (&yi
 }
 
 template <int R, bool SPLIT>
-__device__ void tile_symmetric(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+__device__ __forceinline__ void tile_symmetric(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                                float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                int64_t item, int lane) {
   constexpr int T = kWave * R;
@@ -137,7 +137,7 @@ __device__ void tile_symmetric(const float2* __restrict__ Y, int32_t n, int32_t 
 // SELF (a == b) masks the i == j term by index; MASK_I masks rows past n
 // (only the last block is partial).  Full off-diagonal tiles run unmasked.
 template <int R, bool SPLIT, bool SELF, bool MASK_I>
-__device__ void tile_direct_body(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+__device__ __forceinline__ void tile_direct_body(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                                  float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                  int64_t item, int lane) {
   constexpr int T = kWave * R;
@@ -198,7 +198,7 @@ __device__ void tile_direct_body(const float2* __restrict__ Y, int32_t n, int32_
 }
 
 template <int R, bool SPLIT>
-__device__ void tile_direct(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
+__device__ __forceinline__ void tile_direct(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                             float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                             int64_t item, int lane) {
   const bool partial_a = (int64_t)(a + 1) * (kWave * R) > n;
@@ -215,7 +215,7 @@ __device__ void tile_direct(const float2* __restrict__ Y, int32_t n, int32_t nb,
 // per pass (few registers, so the symmetric path keeps its occupancy), every
 // ordered pair i != j, four interleaved partial sums per coordinate.
 template <int R, bool SPLIT>
-__device__ void tile_diag_light(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a,
+__device__ __forceinline__ void tile_diag_light(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a,
                                 float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                 int64_t item, int lane) {
   constexpr int T = kWave * R;
@@ -317,7 +317,7 @@ hipError_t launch_repulsion_r(const Workspace& ws, int32_t n, const float2* Y, i
 constexpr int kZThreads = 1024;
 
 template <bool SPLIT>
-__device__ void zsum_block(const double* __restrict__ zpart, const float* __restrict__ zpart32, int64_t n_items,
+__device__ __forceinline__ void zsum_block(const double* __restrict__ zpart, const float* __restrict__ zpart32, int64_t n_items,
                            double* __restrict__ Z) {
   __shared__ double sh64[kZThreads];
   __shared__ float sh32[kZThreads];
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ z
 constexpr int kRowLanes = 8;
 
 template <int LANES, bool SPLIT>
-__device__ void attract_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+__device__ __forceinline__ void attract_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                             const float* __restrict__ P, const float2* __restrict__ Y, int32_t i, int sub,
                             double2* __restrict__ out) {
   const int32_t b = row_ptr[i], e_end = row_ptr[i + 1];
@@ -619,11 +619,23 @@ RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
     const int64_t nb = (n + kWave * r - 1) / (kWave * r);
     return p.variant == TSGNE_REPULSION_DIRECT ? nb * nb : nb * (nb + 1) / 2;
   };
-  if (R != 4 && R != 8 && R != 16) {
-    // Largest tile that still leaves ~8 waves of work per SIMD (1024 SIMDs).
-    R = 4;
-    if (items_for(16) >= 8192) R = 16;
-    else if (items_for(8) >= 8192) R = 8;
+  if (!tile_rows_supported(R)) {
+    // Cost model: rounds of 4096 resident waves (4 per SIMD) times the tile
+    // area, divided by the per-pair efficiency of that tile relative to R = 16
+    // (measured on MI355X at 300K nodes: R = 8 and 12 run ~0.84x as fast; the
+    // R = 4 figure is an estimate).  Small graphs get small tiles (more waves
+    // in flight), large graphs the tile whose count fills the last round best.
+    const int32_t rs[6] = {16, 15, 14, 12, 8, 4};
+    const double eff[6] = {1.0, 1.0, 1.0, 0.83, 0.84, 0.7};
+    double best = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      const double T = (double)(kWave * rs[k]);
+      const double cost = (double)((items_for(rs[k]) + 4095) / 4096) * T * T / eff[k];
+      if (best == 0.0 || cost < best) {
+        best = cost;
+        R = rs[k];
+      }
+    }
   }
   p.R = R;
   p.T = kWave * R;
@@ -637,6 +649,9 @@ hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int
     case 4: return launch_repulsion_r<4>(ws, n, Y, precision, s);
     case 8: return launch_repulsion_r<8>(ws, n, Y, precision, s);
     case 16: return launch_repulsion_r<16>(ws, n, Y, precision, s);
+    case 12: return launch_repulsion_r<12>(ws, n, Y, precision, s);
+    case 14: return launch_repulsion_r<14>(ws, n, Y, precision, s);
+    case 15: return launch_repulsion_r<15>(ws, n, Y, precision, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -714,6 +729,9 @@ hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStre
       case 4: e = launch_batch_repulse_r<4>(bp, split, s); break;
       case 8: e = launch_batch_repulse_r<8>(bp, split, s); break;
       case 16: e = launch_batch_repulse_r<16>(bp, split, s); break;
+      case 12: e = launch_batch_repulse_r<12>(bp, split, s); break;
+      case 14: e = launch_batch_repulse_r<14>(bp, split, s); break;
+      case 15: e = launch_batch_repulse_r<15>(bp, split, s); break;
       default: e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
