@@ -260,13 +260,61 @@ def run_serve(args) -> int:
     return 0
 
 
+def run_sparse(args) -> int:
+    """HBM microbenchmark of the sparse phase: the attraction kernels on a
+    10M-node SBM (average degree 10, ~100M stored entries)."""
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    dev = torch.device("cuda:0")
+    n = args.sparse_nodes
+    log("generating SBM with %d nodes" % n)
+    edges, labels = synth.sbm_sparse(n, 100, 10.0, 0.18, synth.MASTER_SEED + 6)
+    X = synth.embedding(labels, 8, 0.5, synth.MASTER_SEED + 6)
+    Y0 = synth.initial_layout(n, synth.MASTER_SEED + 6) * 1000.0
+    rp, col = tsgne.tsgne_csr_from_edges(n, edges)
+    nnz = col.shape[0]
+    d_rp, d_col = torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev)
+    d_X, d_Y = torch.from_numpy(X).to(dev), torch.from_numpy(Y0).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = tsgne.tsgne_build_P(d_rp, d_col, d_X, 30.0)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    A = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        tsgne.tsgne_attraction(g, d_Y, tsgne.TSGNE_PREC_SPLIT, A)
+    g.set_timing(True)
+    reps = 20
+    for _ in range(reps):
+        tsgne.tsgne_attraction(g, d_Y, tsgne.TSGNE_PREC_SPLIT, A)
+    ms, launches = g.timing()["attract"]
+    avg_s = ms / launches / 1e3
+    alg_bytes = 4 * (n + 1) + 8 * nnz + 8 * n + 16 * n
+    result = {
+        "metric": "attraction kernel algorithmic HBM GB/s (sparse phase microbenchmark)",
+        "value": alg_bytes / avg_s / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 3,
+        "ms_per_step": avg_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (FP64 row sums)", "data": "synthetic",
+        "config": {"workload": "sparse", "nodes": n, "stored_entries": int(nnz), "build_P_s": build_s,
+                   "algorithmic_bytes": alg_bytes},
+        "roofline": {"bound": "hbm", "achieved": alg_bytes / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": alg_bytes / avg_s / 8e12, "traffic": None},
+    }
+    print(json.dumps(result), flush=True)
+    g.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256 or serve")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve or sparse")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
+    ap.add_argument("--sparse-nodes", type=int, default=10_000_000, help="sparse: nodes of the SBM")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
     ap.add_argument("--repulsion", default="auto", choices=["auto", "direct", "symmetric"])
     ap.add_argument("--tile-rows", type=int, default=0)
@@ -291,6 +339,8 @@ def main() -> int:
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "sparse":
+        return run_sparse(args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

@@ -157,6 +157,18 @@ TSGNE_API tsgne_status tsgne_gradient(tsgne_graph* g, const float* Y_d, float al
                             double* Z_d, void* stream);
 
 /*
+ * The attractive half of the gradient of eq. (5), per row i:
+ *   A_i = sum over stored entries j of p_ij * w_ij * (y_i - y_j)
+ * (unscaled: the gradient is 4 (alpha A_i - R_i / Z)).  Y_d float32[n][2]
+ * (read), A_d float64[n][2] (written; FP32 arithmetic per entry, accumulated
+ * in FP64 for TSGNE_PREC_SPLIT, all FP32 for TSGNE_PREC_FP32, stored as
+ * float64 either way).  Needs no repulsion workspace.  Asynchronous.
+ * Errors: E_INVAL, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_attraction(tsgne_graph* g, const float* Y_d, int32_t precision, double* A_d,
+                                        void* stream);
+
+/*
  * One optimisation step at index t: the gradient above with alpha =
  * early_exaggeration if t < exaggeration_iters else 1, then per coordinate
  *   gain <- (g * u < 0) ? gain + 0.2 : 0.8 * gain;  gain <- max(gain, min_gain);

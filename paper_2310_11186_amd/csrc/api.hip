@@ -215,7 +215,7 @@ tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipSt
   }
   {
     Timed tm(g, TSGNE_PHASE_ATTRACT, s);
-    TSGNE_HIP(launch_attract(g, Y2, precision, s), "launch attraction");
+    TSGNE_HIP(launch_attract(g, Y2, precision, g->ws.attract, s), "launch attraction");
   }
   return TSGNE_OK;
 }
@@ -470,6 +470,19 @@ tsgne_status tsgne_gradient(tsgne_graph* g, const float* Y_d, float alpha, const
   TSGNE_HIP(launch_update(g, nullptr, nullptr, nullptr, alpha, 0.f, 0.f, 0.f, p->precision, false,
                           reinterpret_cast<float2*>(grad_d), Z_d, s),
             "launch gradient");
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_attraction(tsgne_graph* g, const float* Y_d, int32_t precision, double* A_d, void* stream) {
+  if (tsgne_status st = check_graph(g)) return st;
+  if (!Y_d || !A_d) return fail(TSGNE_E_INVAL, "null pointer");
+  if (precision != TSGNE_PREC_SPLIT && precision != TSGNE_PREC_FP32)
+    return fail(TSGNE_E_INVAL, "precision must be TSGNE_PREC_SPLIT or TSGNE_PREC_FP32");
+  DeviceGuard dg(g->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Timed tm(g, TSGNE_PHASE_ATTRACT, s);
+  TSGNE_HIP(launch_attract(g, reinterpret_cast<const float2*>(Y_d), precision, reinterpret_cast<double2*>(A_d), s),
+            "launch attraction");
   return TSGNE_OK;
 }
 

@@ -207,7 +207,7 @@ hipError_t launch_symmetrise(const int32_t* mirror, int64_t nnz, const double* p
 
 hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s);
 hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s);
-hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, hipStream_t s);
+hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, double2* out, hipStream_t s);
 hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gains, float alpha, float momentum,
                          float eta, float min_gain, int precision, bool do_update, float2* grad_out, double* Z_out,
                          hipStream_t s);

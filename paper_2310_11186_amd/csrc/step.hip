@@ -354,22 +354,38 @@ constexpr int kRowLanes = 8;
 
 template <int LANES, bool SPLIT>
 __device__ __forceinline__ void attract_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                            const float* __restrict__ P, const float2* __restrict__ Y, int32_t i, int sub,
-                            double2* __restrict__ out) {
+                                            const float* __restrict__ P, const float2* __restrict__ Y, int32_t i,
+                                            int sub, double2* __restrict__ out) {
+  constexpr int U = 4;  // entries per lane whose loads are issued together
   const int32_t b = row_ptr[i], e_end = row_ptr[i + 1];
   const float2 yi = Y[i];
   double ax = 0.0, ay = 0.0;
   float fx = 0.f, fy = 0.f;
-  for (int32_t e = b + sub; e < e_end; e += LANES) {
-    const float2 yj = Y[col[e]];
-    const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-    const float pw = P[e] * student_w(dx, dy);
-    if (SPLIT) {
-      ax += (double)(pw * dx);
-      ay += (double)(pw * dy);
-    } else {
-      fx = __builtin_fmaf(pw, dx, fx);
-      fy = __builtin_fmaf(pw, dy, fy);
+  for (int32_t e0 = b + sub; e0 < e_end; e0 += U * LANES) {
+    int32_t j[U];
+    float p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t e = e0 + u * LANES;
+      j[u] = e < e_end ? col[e] : i;
+      p[u] = e < e_end ? P[e] : 0.f;
+    }
+    float2 yj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) yj[u] = Y[j[u]];
+    // entries in increasing order per lane, exactly as a one-at-a-time loop
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * LANES >= e_end) break;
+      const float dx = yi.x - yj[u].x, dy = yi.y - yj[u].y;
+      const float pw = p[u] * student_w(dx, dy);
+      if (SPLIT) {
+        ax += (double)(pw * dx);
+        ay += (double)(pw * dy);
+      } else {
+        fx = __builtin_fmaf(pw, dx, fx);
+        fy = __builtin_fmaf(pw, dy, fy);
+      }
     }
   }
   if (!SPLIT) {
@@ -426,14 +442,22 @@ __device__ __forceinline__ void update_row(const float2* __restrict__ part, int3
   const float2* __restrict__ pp = part + (int64_t)k * nb * T + off;
   double rx = 0.0, ry = 0.0;
   float sx = 0.f, sy = 0.f;
-  for (int32_t o = 0; o < nb; ++o) {
-    const float2 v = pp[(int64_t)o * T];
-    if (SPLIT) {
-      rx += v.x;
-      ry += v.y;
-    } else {
-      sx += v.x;
-      sy += v.y;
+  constexpr int kBatchLoads = 8;  // partials whose loads are issued together
+  for (int32_t o0 = 0; o0 < nb; o0 += kBatchLoads) {
+    float2 v[kBatchLoads];
+#pragma unroll
+    for (int u = 0; u < kBatchLoads; ++u) v[u] = (o0 + u < nb) ? pp[(int64_t)(o0 + u) * T] : make_float2(0.f, 0.f);
+    // added in block order, exactly as a one-at-a-time loop
+#pragma unroll
+    for (int u = 0; u < kBatchLoads; ++u) {
+      if (o0 + u >= nb) break;
+      if (SPLIT) {
+        rx += v[u].x;
+        ry += v[u].y;
+      } else {
+        sx += v[u].x;
+        sy += v[u].y;
+      }
     }
   }
   const double2 A = attract[i];
@@ -664,24 +688,22 @@ hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, hipStream_t s) {
+hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, double2* out, hipStream_t s) {
   const bool split = precision != TSGNE_PREC_FP32;
   const unsigned lb = blocks_for((int64_t)g->n * kRowLanes, kBlock);
   if (split)
-    hipLaunchKernelGGL(k_attract_light<true>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n,
-                       g->ws.attract);
+    hipLaunchKernelGGL(k_attract_light<true>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
   else
-    hipLaunchKernelGGL(k_attract_light<false>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n,
-                       g->ws.attract);
+    hipLaunchKernelGGL(k_attract_light<false>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g->n_heavy == 0) return e;
   const unsigned hb = blocks_for(g->n_heavy, kWavesPerBlock);
   if (split)
     hipLaunchKernelGGL(k_attract_heavy<true>, dim3(hb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->heavy,
-                       g->n_heavy, g->ws.attract);
+                       g->n_heavy, out);
   else
     hipLaunchKernelGGL(k_attract_heavy<false>, dim3(hb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->heavy,
-                       g->n_heavy, g->ws.attract);
+                       g->n_heavy, out);
   return hipGetLastError();
 }
 

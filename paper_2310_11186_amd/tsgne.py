@@ -36,7 +36,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
-    "tsgne_kl", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
+    "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
     "tsgne_server_wait", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
     "tsgne_server_destroy",
@@ -131,6 +131,7 @@ def lib():
             "tsgne_step": (st, [vp, vp, vp, vp, i32, P, vp, vp, vp]),
             "tsgne_run": (st, [vp, vp, i32, P, vp, vp]),
             "tsgne_kl": (st, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_attraction": (st, [vp, vp, i32, vp, vp]),
             "tsgne_batch_run": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32), i32, P, vp]),
             "tsgne_autotune": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_double), vp]),
@@ -296,6 +297,17 @@ def tsgne_gradient(g: Graph, Y, alpha: float = 1.0, params: tsgne_params | None 
     _check(lib().tsgne_gradient(g.handle, _ptr(Y), float(alpha), ctypes.byref(params) if params else None,
                                 _ptr(grad), _ptr(Z), _stream(stream)))
     return grad, Z
+
+
+def tsgne_attraction(g: Graph, Y, precision: int = TSGNE_PREC_SPLIT, A=None, stream=None):
+    """A_i = sum_j p_ij w_ij (y_i - y_j) at Y (float32[n, 2]); returns float64[n, 2]."""
+    import torch
+    n, _ = g.info()
+    _require(Y, torch.float32, (n, 2), "Y")
+    A = torch.empty((n, 2), dtype=torch.float64, device=Y.device) if A is None else A
+    _require(A, torch.float64, (n, 2), "A")
+    _check(lib().tsgne_attraction(g.handle, _ptr(Y), int(precision), _ptr(A), _stream(stream)))
+    return A
 
 
 def tsgne_step(g: Graph, Y, upd, gains, t: int, params: tsgne_params, grad_out=None, Z_out=None, stream=None):

@@ -166,6 +166,20 @@ def test_gradient_and_Z_match_oracle(gpu, kind, n, R, variant):
             assert abs(Z.item() / oZ - 1) <= 1e-6, (name, Z.item(), oZ)
 
 
+@pytest.mark.parametrize("kind,n", [("dcsbm", 3001), ("sbm2k", 2000)])
+def test_attraction_matches_oracle(gpu, kind, n):
+    # the gradient is affine in alpha, so the oracle's attraction is
+    # (g(alpha = 1) - g(alpha = 0)) / 4
+    c = make_case(kind, n, gpu, 30.0, seed=6)
+    Y = states(n, 4)["spread1"]
+    A = tsgne.tsgne_attraction(c.graph, c.Y(Y)).cpu().numpy()
+    g1, _ = oracle.gradient(c.orp, c.ocol, c.oP, Y.astype(np.float64), 1.0)
+    g0, _ = oracle.gradient(c.orp, c.ocol, c.oP, Y.astype(np.float64), 0.0)
+    assert rel_l2(A, (g1 - g0) / 4.0) <= 1e-6
+    A32 = tsgne.tsgne_attraction(c.graph, c.Y(Y), tsgne.TSGNE_PREC_FP32).cpu().numpy()
+    assert rel_l2(A32, (g1 - g0) / 4.0) <= 1e-5
+
+
 def test_gradient_all_fp32_mode_is_close(gpu):
     c = make_case("dcsbm", 3001, gpu, 30.0, seed=5)
     p = tsgne.tsgne_params_default(precision=tsgne.TSGNE_PREC_FP32)
