@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "mirror", "edge_sqdist", "calibrate",
+    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "mirror", "edge_sqdist", "calibrate",
     "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
@@ -56,6 +56,7 @@ def lib():
             "oracle_set_threads": (None, [ctypes.c_int]),
             "oracle_csr_from_edges": (ctypes.c_int, [i32, i64, vp, vp, vp, vp]),
             "oracle_mirror": (ctypes.c_int, [i32, i64, vp, vp, vp]),
+            "oracle_knn_graph": (ctypes.c_int, [i32, vp, vp, i32, vp, vp, vp]),
             "oracle_edge_sqdist": (None, [i32, vp, vp, vp, i32, vp]),
             "oracle_calibrate": (None, [i32, vp, vp, dbl, vp, vp]),
             "oracle_symmetrise": (ctypes.c_int, [i32, vp, vp, vp, vp]),
@@ -112,6 +113,20 @@ def csr_from_edges(n: int, edges) -> tuple[np.ndarray, np.ndarray]:
     if rc != 0:
         raise OracleError("csr_from_edges failed (%d)" % rc)
     return row_ptr, col[: nnz.value].copy()
+
+
+def knn_graph(row_ptr, col, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """Canonical CSR of G_knn,G (§2.2, eq. (7)): i ~ j when either is among the
+    other's k smallest nodes by (BFS hop distance, id)."""
+    row_ptr, col = _i32(row_ptr), _i32(col)
+    n = row_ptr.shape[0] - 1
+    out_rp = np.zeros(n + 1, np.int32)
+    out_col = np.zeros(max(2 * n * k, 1), np.int32)
+    nnz = ctypes.c_int64(0)
+    rc = lib().oracle_knn_graph(n, _p(row_ptr), _p(col), int(k), _p(out_rp), _p(out_col), ctypes.byref(nnz))
+    if rc != 0:
+        raise OracleError("knn_graph failed (%d)" % rc)
+    return out_rp, out_col[: nnz.value].copy()
 
 
 def mirror(row_ptr, col) -> np.ndarray:

@@ -100,6 +100,11 @@ int oracle_csr_from_edges(int32_t n, int64_t m, const int32_t* uv, int32_t* row_
   return ORACLE_OK;
 }
 
+static int cmp_int32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
 /* Position of column j in row i (ascending), or -1. */
 static int64_t find_in_row(const int32_t* row_ptr, const int32_t* col, int32_t i, int32_t j) {
   int64_t lo = row_ptr[i], hi = row_ptr[i + 1] - 1;
@@ -135,6 +140,64 @@ int oracle_mirror(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t*
     }
   }
   return ORACLE_OK;
+}
+
+/*
+ * The t-SGNE neighbourhood graph G_knn,G of §2.2, eq. (7): v_i and v_j are
+ * joined when one is among the first k nearest neighbours of the other on G,
+ * nearest by breadth-first search.  Reading: the first k neighbours of i are
+ * the k smallest nodes j != i under (hop distance from i, node id) -- fewer
+ * when i's component is smaller.  Each BFS runs level by level and stops once
+ * a completed level brings the count to k.  The result is the canonical
+ * symmetric CSR of the union (out_col must hold 2*n*k entries).
+ */
+int oracle_knn_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k, int32_t* out_row_ptr,
+                     int32_t* out_col, int64_t* out_nnz) {
+  if (n < 0 || k < 1) return ORACLE_EINVAL;
+  int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t* uv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * (int64_t)n * k + 2));
+  if (!dist || !queue || !uv) {
+    free(dist);
+    free(queue);
+    free(uv);
+    return ORACLE_ENOMEM;
+  }
+  for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+  int64_t m = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t head = 0, tail = 0, taken = 0;
+    queue[tail++] = i;
+    dist[i] = 0;
+    while (head < tail && taken < k) {
+      /* expand one whole level: queue[head..level_end) */
+      int32_t level_end = tail, next_begin = tail;
+      for (; head < level_end; ++head) {
+        int32_t u = queue[head];
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+          int32_t v = col[e];
+          if (dist[v] < 0) {
+            dist[v] = dist[u] + 1;
+            queue[tail++] = v;
+          }
+        }
+      }
+      /* the new level, in ascending id order */
+      int32_t cnt = tail - next_begin;
+      qsort(queue + next_begin, (size_t)cnt, sizeof(int32_t), cmp_int32);
+      for (int32_t t = next_begin; t < tail && taken < k; ++t, ++taken) {
+        uv[2 * m] = i;
+        uv[2 * m + 1] = queue[t];
+        ++m;
+      }
+    }
+    for (int32_t t = 0; t < tail; ++t) dist[queue[t]] = -1;
+  }
+  int rc = oracle_csr_from_edges(n, m, uv, out_row_ptr, out_col, out_nnz);
+  free(dist);
+  free(queue);
+  free(uv);
+  return rc;
 }
 
 /* ------------------------------------------------------------------ */

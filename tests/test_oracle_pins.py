@@ -367,3 +367,50 @@ def test_oracle_threads_do_not_change_results():
     b, zb = oracle.gradient(row_ptr, col, P, Y)
     oracle.set_threads(k)
     assert np.array_equal(a, b) and za == zb
+
+
+# ---------------------------------------------------------------------------
+# Neighbourhood graph G_knn,G (§2.2, eq. (7))
+# ---------------------------------------------------------------------------
+
+def brute_knn(n, edges, k):
+    """N_k(i) from all-pairs hop distances (scipy's BFS), sorted by (dist, id)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    e = np.asarray(edges).reshape(-1, 2)
+    A = coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
+    D = shortest_path(A, directed=False, unweighted=True)
+    adj = np.zeros((n, n), bool)
+    for i in range(n):
+        cand = [(D[i, j], j) for j in range(n) if j != i and np.isfinite(D[i, j])]
+        cand.sort()
+        for _, j in cand[:k]:
+            adj[i, j] = adj[j, i] = True
+    return adj
+
+
+@pytest.mark.parametrize("seed,n,k", [(0, 30, 3), (1, 40, 6), (2, 25, 30), (3, 60, 1)])
+def test_knn_graph_against_all_pairs_hop_distances(seed, n, k):
+    g = synth.small_sbm(n, 3, 3.0, 2, seed)
+    edges = np.concatenate([g.edges, [[0, n - 1]]])       # a chain link across communities
+    rp, col = oracle.csr_from_edges(n, edges)
+    krp, kcol = oracle.knn_graph(rp, col, k)
+    adj = brute_knn(n, edges, k)
+    r, c = np.nonzero(adj)
+    assert np.array_equal(kcol, c)
+    assert np.array_equal(krp, np.concatenate([[0], np.cumsum(adj.sum(1))]))
+
+
+def test_knn_graph_special_cases():
+    # path 0-1-2-3-4: k = 1 keeps the path; k = 2 adds the 2-hop chords; k >= 4 is complete
+    edges = np.array([[0, 1], [1, 2], [2, 3], [3, 4]])
+    rp, col = oracle.csr_from_edges(5, edges)
+    krp, kcol = oracle.knn_graph(rp, col, 1)
+    # node 1's nearest is 0 (tie with 2, smaller id), node 2's is 1, node 3's is 2, node 4's is 3
+    assert np.array_equal(krp, rp) and np.array_equal(kcol, col)
+    krp, kcol = oracle.knn_graph(rp, col, 4)
+    assert np.array_equal(np.diff(krp), [4] * 5)
+    # isolated nodes stay isolated; an edge's two ends always join
+    rp, col = oracle.csr_from_edges(4, np.array([[1, 2]]))
+    krp, kcol = oracle.knn_graph(rp, col, 3)
+    assert np.array_equal(krp, [0, 0, 1, 2, 2]) and np.array_equal(kcol, [2, 1])
