@@ -104,6 +104,28 @@ TSGNE_API tsgne_status tsgne_csr_from_edges(int32_t n, int64_t m, const int32_t*
                                   int64_t* nnz_out);
 
 /*
+ * The t-SGNE neighbourhood graph G_knn,G of section 2.2, eq. (7): nodes i and
+ * j are joined when one is among the first k nearest neighbours of the other
+ * on G, nearest by breadth-first search.  Reading: the first k neighbours of i
+ * are the k smallest nodes j != i under (hop distance from i, node id), fewer
+ * when i's component is smaller.  The result can be passed to tsgne_build_P in
+ * place of G's own CSR.
+ *   n, nnz, row_ptr_d, col_d -- G as a canonical symmetric CSR (device), as
+ *                               for tsgne_build_P
+ *   k                        -- 1 .. 256
+ *   knn_row_ptr_d            -- int32[n+1] (device, written)
+ *   knn_col_d                -- int32[knn_capacity] (device, written); 2*n*k
+ *                               always suffices
+ *   *knn_nnz                 -- number of stored entries of the result (also
+ *                               set when the capacity is too small)
+ * Synchronising.  Errors: E_INVAL (bad sizes, k, capacity too small),
+ * E_GRAPH (input CSR not canonical/symmetric), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_knn_graph(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d,
+                                       int32_t k, int32_t* knn_row_ptr_d, int32_t* knn_col_d, int64_t knn_capacity,
+                                       int64_t* knn_nnz, void* stream);
+
+/*
  * Builds the joint affinities P of eq. (3) from the conditional affinities of
  * eq. (2) over each node's graph neighbours (section 2.2), with the bandwidth
  * of each row set by bisection so that its perplexity equals `perplexity`

@@ -34,7 +34,8 @@ TSGNE_REPULSION_SYMMETRIC = 2
 
 # every symbol include/tsgne.h declares
 EXPORTED = (
-    "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_build_P",
+    "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
+    "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
@@ -124,6 +125,7 @@ def lib():
             "tsgne_status_string": (ctypes.c_char_p, [st]),
             "tsgne_csr_from_edges": (st, [i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]),
             "tsgne_build_P": (st, [i32, i64, vp, vp, vp, i32, ctypes.c_float, vp, ctypes.POINTER(vp)]),
+            "tsgne_knn_graph": (st, [i32, i64, vp, vp, i32, vp, vp, i64, ctypes.POINTER(i64), vp]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -216,6 +218,21 @@ def tsgne_csr_from_edges(n: int, edges) -> tuple[np.ndarray, np.ndarray]:
     _check(lib().tsgne_csr_from_edges(n, m, uv.ctypes.data, row_ptr.ctypes.data, col.ctypes.data,
                                       ctypes.byref(nnz)))
     return row_ptr, col[: nnz.value].copy()
+
+
+def tsgne_knn_graph(row_ptr, col, k: int, stream=None):
+    """Device CSR (row_ptr, col) of G_knn,G for a device CSR of G (int32 tensors)."""
+    import torch
+    _require(row_ptr, torch.int32, name="row_ptr")
+    _require(col, torch.int32, name="col")
+    n = row_ptr.shape[0] - 1
+    out_rp = torch.empty(n + 1, dtype=torch.int32, device=row_ptr.device)
+    cap = 2 * n * int(k)
+    out_col = torch.empty(max(cap, 1), dtype=torch.int32, device=row_ptr.device)
+    nnz = ctypes.c_int64(0)
+    _check(lib().tsgne_knn_graph(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, int(k),
+                                 _ptr(out_rp), _ptr(out_col), cap, ctypes.byref(nnz), _stream(stream)))
+    return out_rp, out_col[: nnz.value].clone()
 
 
 class Graph:
