@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "mirror", "edge_sqdist", "calibrate",
+    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "mirror", "edge_sqdist", "calibrate",
     "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
@@ -57,6 +57,7 @@ def lib():
             "oracle_csr_from_edges": (ctypes.c_int, [i32, i64, vp, vp, vp, vp]),
             "oracle_mirror": (ctypes.c_int, [i32, i64, vp, vp, vp]),
             "oracle_knn_graph": (ctypes.c_int, [i32, vp, vp, i32, vp, vp, vp]),
+            "oracle_shortest_path_embedding": (ctypes.c_int, [i32, vp, vp, i32, vp, dbl, vp]),
             "oracle_edge_sqdist": (None, [i32, vp, vp, vp, i32, vp]),
             "oracle_calibrate": (None, [i32, vp, vp, dbl, vp, vp]),
             "oracle_symmetrise": (ctypes.c_int, [i32, vp, vp, vp, vp]),
@@ -127,6 +128,17 @@ def knn_graph(row_ptr, col, k: int) -> tuple[np.ndarray, np.ndarray]:
     if rc != 0:
         raise OracleError("knn_graph failed (%d)" % rc)
     return out_rp, out_col[: nnz.value].copy()
+
+
+def shortest_path_embedding(row_ptr, col, targets, l0: float) -> np.ndarray:
+    """X float32[n, d]: hop distance to each target if <= l0, else l0 + 1 (§2.3, eq. (8))."""
+    row_ptr, col, targets = _i32(row_ptr), _i32(col), _i32(targets)
+    n, d = row_ptr.shape[0] - 1, targets.shape[0]
+    X = np.zeros((n, d), np.float32)
+    rc = lib().oracle_shortest_path_embedding(n, _p(row_ptr), _p(col), d, _p(targets), float(l0), _p(X))
+    if rc != 0:
+        raise OracleError("shortest_path_embedding failed (%d)" % rc)
+    return X
 
 
 def mirror(row_ptr, col) -> np.ndarray:

@@ -200,6 +200,54 @@ int oracle_knn_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, int3
   return rc;
 }
 
+/*
+ * ShortestPath graph embedding (§2.3, eq. (8)): for target nodes t_0..t_{d-1},
+ * E_ij = (hop distance between v_i and t_j) if it is at most l0, otherwise
+ * l0 + 1 (also when no path exists).  Readings: eq. (8) writes the condition
+ * on "d", read as d_ij; the prose says "less than l0" while the equation says
+ * "<= l0", and the equation is followed; l0 is the real number given (the
+ * paper's default is sqrt(|E|)).  One BFS from each target.  X is float32
+ * [n][d] row-major.
+ */
+int oracle_shortest_path_embedding(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t d,
+                                   const int32_t* targets, double l0, float* X) {
+  if (n < 0 || d < 1) return ORACLE_EINVAL;
+  int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  if (!dist || !queue) {
+    free(dist);
+    free(queue);
+    return ORACLE_ENOMEM;
+  }
+  for (int32_t j = 0; j < d; ++j) {
+    int32_t t = targets[j];
+    if (t < 0 || t >= n) {
+      free(dist);
+      free(queue);
+      return ORACLE_EINVAL;
+    }
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    int32_t head = 0, tail = 0;
+    queue[tail++] = t;
+    dist[t] = 0;
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+        int32_t v = col[e];
+        if (dist[v] < 0) {
+          dist[v] = dist[u] + 1;
+          queue[tail++] = v;
+        }
+      }
+    }
+    for (int32_t v = 0; v < n; ++v)
+      X[(int64_t)v * d + j] = (dist[v] >= 0 && (double)dist[v] <= l0) ? (float)dist[v] : (float)(l0 + 1.0);
+  }
+  free(dist);
+  free(queue);
+  return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Affinities P (§2.1, eqs. (2)-(3)) over graph neighbours (§2.2).      */
 /* ------------------------------------------------------------------ */

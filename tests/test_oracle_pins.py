@@ -414,3 +414,23 @@ def test_knn_graph_special_cases():
     rp, col = oracle.csr_from_edges(4, np.array([[1, 2]]))
     krp, kcol = oracle.knn_graph(rp, col, 3)
     assert np.array_equal(krp, [0, 0, 1, 2, 2]) and np.array_equal(kcol, [2, 1])
+
+
+# ---------------------------------------------------------------------------
+# ShortestPath embedding (§2.3, eq. (8))
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,n,l0", [(0, 50, 2.5), (1, 80, 100.0), (2, 40, 1.0)])
+def test_shortest_path_embedding_against_scipy(seed, n, l0):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    g = synth.small_sbm(n, 3, 2.5, 2, seed)            # sparse enough to leave some nodes unreachable
+    rp, col = oracle.csr_from_edges(n, g.edges)
+    targets = np.random.default_rng(seed).choice(n, 7, replace=False).astype(np.int32)
+    X = oracle.shortest_path_embedding(rp, col, targets, l0)
+    e = g.edges
+    A = coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
+    D = shortest_path(A, directed=False, unweighted=True, indices=targets)   # [d, n]
+    expect = np.where(np.isfinite(D) & (D <= l0), D, l0 + 1.0).T.astype(np.float32)
+    assert np.array_equal(X, expect)
+    assert np.all(X[targets, np.arange(7)] == 0)
