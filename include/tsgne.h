@@ -126,6 +126,30 @@ TSGNE_API tsgne_status tsgne_knn_graph(int32_t n, int64_t nnz, const int32_t* ro
                                        int64_t* knn_nnz, void* stream);
 
 /*
+ * The ShortestPath graph embedding of section 2.3, eq. (8): X[i][j] is the
+ * hop distance between node i and target t_j when it is at most l0, and
+ * l0 + 1 when it is larger or t_j cannot be reached from i.  Readings: the
+ * condition of eq. (8) is on d_ij, and the equation's "at most l0" is
+ * followed.  The paper picks the d targets at random; the caller passes them.
+ * X can be passed to tsgne_build_P as the node embedding.
+ *   n, nnz, row_ptr_d, col_d -- G as a canonical symmetric CSR (device), as
+ *                               for tsgne_build_P
+ *   d                        -- number of targets, 1 .. 256
+ *   targets_d                -- int32[d] (device) node ids in [0, n);
+ *                               repeats allowed
+ *   l0                       -- threshold; a negative value selects the
+ *                               paper's default sqrt(|E|), |E| = nnz / 2
+ *   X_d                      -- float32[n][d] row-major (device, written)
+ *   levels_out               -- nullable; receives the number of search
+ *                               levels launched (at most floor(l0))
+ * Synchronising.  Errors: E_INVAL (bad sizes, NaN l0, a target outside
+ * [0, n)), E_GRAPH (CSR not canonical/symmetric), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_shortest_path_embedding(int32_t n, int64_t nnz, const int32_t* row_ptr_d,
+                                                     const int32_t* col_d, int32_t d, const int32_t* targets_d,
+                                                     double l0, float* X_d, int32_t* levels_out, void* stream);
+
+/*
  * Builds the joint affinities P of eq. (3) from the conditional affinities of
  * eq. (2) over each node's graph neighbours (section 2.2), with the bandwidth
  * of each row set by bisection so that its perplexity equals `perplexity`

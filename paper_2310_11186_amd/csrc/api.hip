@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +28,45 @@ tsgne_status fail(tsgne_status code, const std::string& msg) {
 tsgne_status hip_fail(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? TSGNE_E_NOMEM : TSGNE_E_DEVICE,
               std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+std::mutex g_pool_mutex;
+std::map<int, hipMemPool_t> g_pools;  // one per device, kept until the process ends
+}  // namespace
+
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    auto it = g_pools.find(dev);
+    if (it == g_pools.end()) {
+      hipMemPoolProps props{};
+      props.allocType = hipMemAllocationTypePinned;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      e = hipMemPoolCreate(&pool, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = (uint64_t)1 << 30;  // cached bytes kept across synchronisations
+      e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return e;
+      }
+      g_pools[dev] = pool;
+    } else {
+      pool = it->second;
+    }
+  }
+  return hipMallocFromPoolAsync(p, bytes ? bytes : 1, pool, s);
+}
+
+void scratch_free(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
 }
 
 namespace {
@@ -353,20 +394,23 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
 
   uint32_t* err = nullptr;
   int32_t* counters = nullptr;
+  int2* partial = nullptr;
   double* D = nullptr;
   double* pcond = nullptr;
   struct Scratch {
     uint32_t*& err;
     int32_t*& counters;
+    int2*& partial;
     double*& D;
     double*& pcond;
     ~Scratch() {
       dfree(err);
       dfree(counters);
+      dfree(partial);
       dfree(D);
       dfree(pcond);
     }
-  } scratch{err, counters, D, pcond};
+  } scratch{err, counters, partial, D, pcond};
 
   const int32_t heavy_cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
   TSGNE_HIP(dalloc(&g->row_ptr, (size_t)n + 1), "allocate row_ptr");
@@ -378,6 +422,7 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
   TSGNE_HIP(dalloc(&g->heavy, (size_t)heavy_cap), "allocate heavy rows");
   TSGNE_HIP(dalloc(&err, 1), "allocate error word");
   TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
+  TSGNE_HIP(dalloc(&partial, (size_t)row_check_blocks(n)), "allocate row counts");
   TSGNE_HIP(dalloc(&D, (size_t)nnz), "allocate distances");
   TSGNE_HIP(dalloc(&pcond, (size_t)nnz), "allocate conditional affinities");
 
@@ -389,7 +434,8 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
   TSGNE_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s), "clear counters");
 
   // 1. row_ptr must be valid before any kernel indexes col with it.
-  TSGNE_HIP(launch_check_rows(g->row_ptr, n, nnz, err, counters, g->heavy, s), "launch row check");
+  TSGNE_HIP(launch_check_rows(g->row_ptr, n, nnz, kHeavyDegree, err, counters, partial, g->heavy, nullptr, heavy_cap, s),
+            "launch row check");
   uint32_t host_err = 0;
   int32_t host_counters[2] = {0, 0};
   TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");

@@ -10,64 +10,208 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ __launch_bounds__(kBlock) void k_check_rows(const int32_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
-                                                       uint32_t* __restrict__ err, int32_t* __restrict__ counters,
-                                                       int32_t* __restrict__ heavy, int32_t heavy_cap) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+// Row checks and counts without contended atomics (atomics on one address
+// serialise across the whole device): per-block counts, one block turns
+// them into offsets, then each block writes its selected rows in order.
+__device__ __forceinline__ bool row_ok(const int32_t* __restrict__ row_ptr, int32_t i, int32_t n, int64_t nnz,
+                                       int64_t* deg) {
   const int64_t a = row_ptr[i], b = row_ptr[i + 1];
   bool bad = b < a || a < 0 || b > nnz;
   if (i == 0 && a != 0) bad = true;
   if (i == n - 1 && b != nnz) bad = true;
-  if (bad) {
-    atomicOr(err, kErrRowPtr);
-    return;
+  *deg = b - a;
+  return !bad;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_counts(const int32_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
+                                                       int32_t threshold, uint32_t* __restrict__ err,
+                                                       int2* __restrict__ partial) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  bool nonempty = false, sel = false;
+  if (i < n) {
+    int64_t deg;
+    if (!row_ok(row_ptr, i, n, nnz, &deg)) {
+      atomicOr(err, kErrRowPtr);
+    } else {
+      nonempty = deg > 0;
+      sel = deg > threshold;
+    }
   }
-  const int64_t deg = b - a;
-  if (deg > 0) atomicAdd(&counters[0], 1);
-  if (deg > kHeavyDegree) {
-    const int32_t k = atomicAdd(&counters[1], 1);
-    if (k < heavy_cap) heavy[k] = i;
+  const int c_ne = __syncthreads_count(nonempty);
+  const int c_sel = __syncthreads_count(sel);
+  if (threadIdx.x == 0) partial[blockIdx.x] = make_int2(c_ne, c_sel);
+}
+
+constexpr int kScanBlock = 1024;
+constexpr int kRowOfRun = 8;     // entries per thread in k_row_of
+constexpr int kMirrorPer = 4;    // entries per thread in k_mirror
+
+// One block: partial[b].y becomes the number of selected rows in blocks
+// before b; counters = (rows with entries, selected rows).
+__global__ __launch_bounds__(kScanBlock) void k_row_offsets(int2* __restrict__ partial, int32_t blocks,
+                                                            int32_t* __restrict__ counters) {
+  __shared__ int32_t s_sel[kScanBlock / kWave], s_ne[kScanBlock / kWave];
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv = t >> 6;
+  const int32_t per = (blocks + kScanBlock - 1) / kScanBlock;
+  const int32_t lo = min(blocks, t * per), hi = min(blocks, lo + per);
+  int32_t sel = 0, ne = 0;
+  for (int32_t b = lo; b < hi; ++b) {
+    sel += partial[b].y;
+    ne += partial[b].x;
+  }
+  int32_t inc = sel;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t y = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += y;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) ne += __shfl_xor(ne, off, kWave);
+  if (lane == kWave - 1) s_sel[wv] = inc;
+  if (lane == 0) s_ne[wv] = ne;
+  __syncthreads();
+  int32_t base = 0, tot_sel = 0, tot_ne = 0;
+  for (int w = 0; w < kScanBlock / kWave; ++w) {
+    base += (w < wv) ? s_sel[w] : 0;
+    tot_sel += s_sel[w];
+    tot_ne += s_ne[w];
+  }
+  int32_t run = base + inc - sel;
+  for (int32_t b = lo; b < hi; ++b) {
+    const int32_t c = partial[b].y;
+    partial[b].y = run;
+    run += c;
+  }
+  if (t == 0) {
+    counters[0] = tot_ne;
+    counters[1] = tot_sel;
   }
 }
 
-// One thread per stored entry e: its row (binary search in row_ptr, which the
-// previous kernel validated), the checks on its column, and the position of
-// the reverse entry in the column's row.
+__global__ __launch_bounds__(kBlock) void k_row_select(const int32_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
+                                                       int32_t threshold, const int2* __restrict__ partial,
+                                                       int32_t* __restrict__ ids, int4* __restrict__ recs,
+                                                       int32_t cap) {
+  __shared__ int32_t s_wave[kBlock / kWave];
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+  bool sel = false;
+  if (i < n) {
+    int64_t deg;
+    sel = row_ok(row_ptr, i, n, nnz, &deg) && deg > threshold;
+  }
+  const unsigned long long m = __ballot(sel);
+  if (lane == 0) s_wave[wv] = __popcll(m);
+  __syncthreads();
+  int32_t pos = partial[blockIdx.x].y + __popcll(m & ((1ull << lane) - 1));
+  for (int w = 0; w < wv; ++w) pos += s_wave[w];
+  if (sel && pos < cap) {
+    if (ids) ids[pos] = i;
+    if (recs) recs[pos] = make_int4(i, row_ptr[i], row_ptr[i + 1], 0);
+  }
+}
+
+// row_of[e] = the row of entry e: one block per kBlock rows shares out the
+// entries of its rows.  Does nothing when the row check has failed, so it
+// may be queued behind that check without waiting for its result.
+__global__ __launch_bounds__(kBlock) void k_row_of(const int32_t* __restrict__ row_ptr, int32_t n,
+                                                   int32_t* __restrict__ row_of, const uint32_t* __restrict__ err) {
+  __shared__ int32_t s_ptr[kBlock + 1];
+  if (*err & kErrRowPtr) return;
+  const int32_t r0 = blockIdx.x * kBlock;
+  const int32_t rows = min(kBlock, n - r0);
+  for (int t = threadIdx.x; t <= rows; t += kBlock) s_ptr[t] = row_ptr[r0 + t];
+  __syncthreads();
+  const int32_t first = s_ptr[0], end = s_ptr[rows];
+  // kRowOfRun consecutive entries per thread: one search, then a walk
+  for (int32_t e0 = first + threadIdx.x * kRowOfRun; e0 < end; e0 += kBlock * kRowOfRun) {
+    int lo = 0, hi = rows;  // s_ptr[lo] <= e0 < s_ptr[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_ptr[mid] <= e0) lo = mid;
+      else hi = mid;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowOfRun; ++k) {
+      const int32_t e = e0 + k;
+      if (e < end) {
+        while (s_ptr[lo + 1] <= e) ++lo;  // stops below rows since e < s_ptr[rows]
+        row_of[e] = r0 + lo;
+      }
+    }
+  }
+}
+
+// kMirrorPer entries per thread (row from row_of): the checks on each
+// entry's column and the position of the reverse entry in the column's row,
+// with the binary searches of the entries advancing together so that their
+// loads overlap.  Does nothing when the row check has failed.
 __global__ __launch_bounds__(kBlock) void k_mirror(const int32_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col, int32_t n, int64_t nnz,
-                                                   int32_t* __restrict__ mirror, int32_t* __restrict__ row_of,
+                                                   int32_t* __restrict__ mirror, const int32_t* __restrict__ row_of,
                                                    uint32_t* __restrict__ err) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= nnz) return;
-  int32_t lo = 0, hi = n;  // row_ptr[lo] <= e < row_ptr[hi]
-  while (hi - lo > 1) {
-    const int32_t mid = lo + (hi - lo) / 2;
-    if (row_ptr[mid] <= e) lo = mid; else hi = mid;
-  }
-  const int32_t i = lo;
-  row_of[e] = i;
-  const int32_t j = col[e];
+  if (*err & kErrRowPtr) return;  // row_of is not filled after a failed row check
+  const int64_t e0 = (int64_t)blockIdx.x * kBlock * kMirrorPer + threadIdx.x;
+  int64_t lo[kMirrorPer], hi[kMirrorPer], mid[kMirrorPer];
+  int32_t key[kMirrorPer], pos[kMirrorPer];
+  bool live[kMirrorPer];
   uint32_t bits = 0;
-  int32_t pos = -1;
-  if (j < 0 || j >= n) {
-    bits |= kErrColRange;
-  } else {
-    if (j == i) bits |= kErrSelfLoop;
-    if (e > row_ptr[i] && col[e - 1] >= j) bits |= kErrOrder;
-    int64_t l = row_ptr[j], h = (int64_t)row_ptr[j + 1] - 1;
-    while (l <= h) {
-      const int64_t m = l + (h - l) / 2;
-      const int32_t c = col[m];
-      if (c == i) {
-        pos = (int32_t)m;
-        break;
+#pragma unroll
+  for (int k = 0; k < kMirrorPer; ++k) {
+    const int64_t e = e0 + (int64_t)k * kBlock;
+    live[k] = false;
+    pos[k] = -1;
+    lo[k] = 0;
+    hi[k] = -1;
+    key[k] = 0;
+    if (e < nnz) {
+      const int32_t i = row_of[e];
+      const int32_t j = col[e];
+      if (j < 0 || j >= n) {
+        bits |= kErrColRange;
+      } else {
+        if (j == i) bits |= kErrSelfLoop;
+        if (e > row_ptr[i] && col[e - 1] >= j) bits |= kErrOrder;
+        lo[k] = row_ptr[j];
+        hi[k] = (int64_t)row_ptr[j + 1] - 1;
+        key[k] = i;
+        live[k] = lo[k] <= hi[k];
+        if (!live[k]) bits |= kErrAsym;
       }
-      if (c < i) l = m + 1; else h = m - 1;
     }
-    if (pos < 0) bits |= kErrAsym;
   }
-  mirror[e] = pos;
+  bool any = true;
+  while (any) {
+    int32_t c[kMirrorPer];
+#pragma unroll
+    for (int k = 0; k < kMirrorPer; ++k) {
+      if (live[k]) {
+        mid[k] = lo[k] + (hi[k] - lo[k]) / 2;
+        c[k] = col[mid[k]];
+      }
+    }
+    any = false;
+#pragma unroll
+    for (int k = 0; k < kMirrorPer; ++k) {
+      if (live[k]) {
+        if (c[k] == key[k]) {
+          pos[k] = (int32_t)mid[k];
+          live[k] = false;
+        } else {
+          if (c[k] < key[k]) lo[k] = mid[k] + 1;
+          else hi[k] = mid[k] - 1;
+          if (lo[k] > hi[k]) {
+            live[k] = false;
+            bits |= kErrAsym;
+          }
+        }
+        any |= live[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMirrorPer; ++k) {
+    const int64_t e = e0 + (int64_t)k * kBlock;
+    if (e < nnz) mirror[e] = pos[k];
+  }
   if (bits) atomicOr(err, bits);
 }
 
@@ -235,10 +379,15 @@ inline unsigned blocks_for(int64_t work) { return (unsigned)((work + kBlock - 1)
 
 }  // namespace
 
-hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, uint32_t* err, int32_t* counters,
-                             int32_t* heavy, hipStream_t s) {
-  const int32_t cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
-  hipLaunchKernelGGL(k_check_rows, dim3(blocks_for(n)), dim3(kBlock), 0, s, row_ptr, n, nnz, err, counters, heavy,
+int64_t row_check_blocks(int32_t n) { return ((int64_t)n + kBlock - 1) / kBlock; }
+
+hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, int32_t threshold, uint32_t* err,
+                             int32_t* counters, int2* partial, int32_t* ids, int4* recs, int32_t cap,
+                             hipStream_t s) {
+  const int32_t blocks = (int32_t)row_check_blocks(n);
+  hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(kBlock), 0, s, row_ptr, n, nnz, threshold, err, partial);
+  hipLaunchKernelGGL(k_row_offsets, dim3(1), dim3(kScanBlock), 0, s, partial, blocks, counters);
+  hipLaunchKernelGGL(k_row_select, dim3(blocks), dim3(kBlock), 0, s, row_ptr, n, nnz, threshold, partial, ids, recs,
                      cap);
   return hipGetLastError();
 }
@@ -246,7 +395,9 @@ hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, uin
 hipError_t launch_mirror(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz, int32_t* mirror,
                          int32_t* row_of, uint32_t* err, hipStream_t s) {
   if (nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mirror, dim3(blocks_for(nnz)), dim3(kBlock), 0, s, row_ptr, col, n, nnz, mirror, row_of, err);
+  hipLaunchKernelGGL(k_row_of, dim3((unsigned)row_check_blocks(n)), dim3(kBlock), 0, s, row_ptr, n, row_of, err);
+  hipLaunchKernelGGL(k_mirror, dim3(blocks_for((nnz + kMirrorPer - 1) / kMirrorPer)), dim3(kBlock), 0, s, row_ptr, col,
+                     n, nnz, mirror, row_of, err);
   return hipGetLastError();
 }
 

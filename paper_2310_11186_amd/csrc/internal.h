@@ -177,6 +177,21 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// Per-call scratch from a library-owned stream-ordered pool on the current
+// device: up to 1 GiB of freed blocks stays cached in the pool, so repeated
+// calls do not pay for hipMalloc/hipFree.  Usable in stream order on s.
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
+void scratch_free(void* p, hipStream_t s);
+
+// Owns one scratch allocation until the end of a scope.
+struct ScratchBlock {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~ScratchBlock() {
+    if (p) scratch_free(p, s);
+  }
+};
+
 // Makes a device current for the duration of a scope.
 struct DeviceGuard {
   int prev = -1;
@@ -190,12 +205,27 @@ struct DeviceGuard {
 };
 
 tsgne_status validate_params(const tsgne_params* p);
+// Checks on the device that (row_ptr, col) is a canonical symmetric CSR
+// (synchronising; E_GRAPH otherwise).
+tsgne_status validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, hipStream_t s);
+// The same in caller-provided device scratch of validate_csr_bytes(n, nnz).
+size_t validate_csr_bytes(int32_t n, int64_t nnz);
+tsgne_status validate_csr_in(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, void* scratch,
+                             hipStream_t s);
 float effective_eta(const tsgne_graph* g, const tsgne_params* p);
 tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p);
 
 // Launchers (return hipSuccess or the first HIP error).
-hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, uint32_t* err, int32_t* counters,
-                             int32_t* heavy, hipStream_t s);
+// Checks row_ptr (err |= row bit) and selects, in ascending order, the rows
+// of degree above `threshold` into ids (int32) and/or recs (row, first,
+// end, 0), at most cap of them.  counters[0] = rows with entries,
+// counters[1] = selected rows.  partial: int2[row_check_blocks(n)] scratch.
+int64_t row_check_blocks(int32_t n);
+hipError_t launch_check_rows(const int32_t* row_ptr, int32_t n, int64_t nnz, int32_t threshold, uint32_t* err,
+                             int32_t* counters, int2* partial, int32_t* ids, int4* recs, int32_t cap,
+                             hipStream_t s);
+// Fills row_of (the row of every entry) and checks columns and symmetry
+// (err |= column bits); mirror[e] = position of the reverse entry.
 hipError_t launch_mirror(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz, int32_t* mirror,
                          int32_t* row_of, uint32_t* err, hipStream_t s);
 hipError_t launch_sqdist(const int32_t* row_of, const int32_t* col, int64_t nnz, const float* X, int32_t d,

@@ -145,47 +145,44 @@ __global__ __launch_bounds__(kBlock) void k_knn_csr(const uint64_t* __restrict__
 
 unsigned blocks_for(int64_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
 
-// Checks that (row_ptr, col) is a canonical symmetric CSR.
+}  // namespace
+
+size_t validate_csr_bytes(int32_t n, int64_t nnz) {
+  return sizeof(int32_t) * (4 + 2 * (size_t)row_check_blocks(n) + 2 * (size_t)nnz);
+}
+
 tsgne_status validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, hipStream_t s) {
-  uint32_t* err = nullptr;
-  int32_t* counters = nullptr;
-  int32_t* heavy = nullptr;
-  int32_t* mirror = nullptr;
-  int32_t* row_of = nullptr;
-  struct Tmp {
-    uint32_t*& e;
-    int32_t*& c;
-    int32_t*& h;
-    int32_t*& m;
-    int32_t*& r;
-    ~Tmp() {
-      dfree(e);
-      dfree(c);
-      dfree(h);
-      dfree(m);
-      dfree(r);
-    }
-  } tmp{err, counters, heavy, mirror, row_of};
-  TSGNE_HIP(dalloc(&err, 1), "allocate error word");
-  TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
-  TSGNE_HIP(dalloc(&heavy, (size_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1)), "allocate heavy rows");
-  TSGNE_HIP(dalloc(&mirror, (size_t)nnz), "allocate mirror");
-  TSGNE_HIP(dalloc(&row_of, (size_t)nnz), "allocate row index");
-  TSGNE_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s), "clear error word");
-  TSGNE_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s), "clear counters");
-  TSGNE_HIP(launch_check_rows(row_ptr, n, nnz, err, counters, heavy, s), "launch row check");
+  ScratchBlock tmp;
+  tmp.s = s;
+  TSGNE_HIP(scratch_alloc(&tmp.p, validate_csr_bytes(n, nnz), s), "allocate CSR check buffers");
+  return validate_csr_in(n, nnz, row_ptr, col, tmp.p, s);
+}
+
+// Checks that (row_ptr, col) is a canonical symmetric CSR, in scratch of
+// validate_csr_bytes(n, nnz): error word, counters, per-block row counts,
+// mirror, row index.
+tsgne_status validate_csr_in(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, void* scratch,
+                             hipStream_t s) {
+  const int64_t blocks = row_check_blocks(n);
+  int32_t* const buf = static_cast<int32_t*>(scratch);
+  uint32_t* const err = reinterpret_cast<uint32_t*>(buf);
+  int32_t* const counters = buf + 1;
+  int2* const partial = reinterpret_cast<int2*>(buf + 4);
+  int32_t* const mirror = buf + 4 + 2 * blocks;
+  int32_t* const row_of = mirror + nnz;
+  TSGNE_HIP(hipMemsetAsync(buf, 0, 4 * sizeof(int32_t), s), "clear error word and counters");
+  TSGNE_HIP(launch_check_rows(row_ptr, n, nnz, INT32_MAX, err, counters, partial, nullptr, nullptr, 0, s),
+            "launch row check");
+  // the column checks skip themselves when the row check failed
+  TSGNE_HIP(launch_mirror(row_ptr, col, n, nnz, mirror, row_of, err, s), "launch CSR check");
   uint32_t host_err = 0;
   TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
-  TSGNE_HIP(hipStreamSynchronize(s), "synchronise row check");
-  if (host_err) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
-  TSGNE_HIP(launch_mirror(row_ptr, col, n, nnz, mirror, row_of, err, s), "launch CSR check");
-  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
   TSGNE_HIP(hipStreamSynchronize(s), "synchronise CSR check");
+  if (host_err & kErrRowPtr) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
   if (host_err) return fail(TSGNE_E_GRAPH, "CSR is not canonical and symmetric");
   return TSGNE_OK;
 }
 
-}  // namespace
 }  // namespace tsgne
 
 using namespace tsgne;

@@ -35,7 +35,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 # every symbol include/tsgne.h declares
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
-    "tsgne_build_P",
+    "tsgne_shortest_path_embedding", "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
@@ -126,6 +126,8 @@ def lib():
             "tsgne_csr_from_edges": (st, [i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]),
             "tsgne_build_P": (st, [i32, i64, vp, vp, vp, i32, ctypes.c_float, vp, ctypes.POINTER(vp)]),
             "tsgne_knn_graph": (st, [i32, i64, vp, vp, i32, vp, vp, i64, ctypes.POINTER(i64), vp]),
+            "tsgne_shortest_path_embedding": (st, [i32, i64, vp, vp, i32, vp, ctypes.c_double, vp,
+                                                   ctypes.POINTER(i32), vp]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -233,6 +235,22 @@ def tsgne_knn_graph(row_ptr, col, k: int, stream=None):
     _check(lib().tsgne_knn_graph(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, int(k),
                                  _ptr(out_rp), _ptr(out_col), cap, ctypes.byref(nnz), _stream(stream)))
     return out_rp, out_col[: nnz.value].clone()
+
+
+def tsgne_shortest_path_embedding(row_ptr, col, targets, l0: float = -1.0, stream=None):
+    """X float32[n, d] (device) of the ShortestPath embedding (section 2.3, eq. (8)) from a device
+    CSR and device int32 targets; l0 < 0 selects sqrt(|E|).  Returns (X, levels launched)."""
+    import torch
+    _require(row_ptr, torch.int32, name="row_ptr")
+    _require(col, torch.int32, name="col")
+    _require(targets, torch.int32, name="targets")
+    n, d = row_ptr.shape[0] - 1, targets.shape[0]
+    X = torch.empty((max(n, 0), d), dtype=torch.float32, device=row_ptr.device)
+    levels = ctypes.c_int32(0)
+    _check(lib().tsgne_shortest_path_embedding(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None,
+                                               d, _ptr(targets), float(l0), _ptr(X), ctypes.byref(levels),
+                                               _stream(stream)))
+    return X, levels.value
 
 
 class Graph:

@@ -83,5 +83,13 @@ def test_argument_validation_before_device_work():
     assert L.tsgne_run(None, dummy, 10, ctypes.byref(p), None, None) == tsgne.TSGNE_E_INVAL
     k = ctypes.c_double(0)
     assert L.tsgne_kl(None, dummy, ctypes.byref(k), None) == tsgne.TSGNE_E_INVAL
+    lv = ctypes.c_int32(7)
+    sp = L.tsgne_shortest_path_embedding
+    assert sp(5, 4, dummy, dummy, 0, dummy, 2.0, dummy, ctypes.byref(lv), None) == tsgne.TSGNE_E_INVAL   # d < 1
+    assert lv.value == 0
+    assert sp(5, 4, dummy, dummy, 257, dummy, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL             # d > 256
+    assert sp(5, 4, dummy, dummy, 3, dummy, float("nan"), dummy, None, None) == tsgne.TSGNE_E_INVAL      # NaN l0
+    assert sp(5, 4, dummy, dummy, 3, None, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL                # targets
+    assert sp(0, 0, dummy, dummy, 3, dummy, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL               # n < 1
     assert L.tsgne_graph_free(None) == tsgne.TSGNE_OK
     assert L.tsgne_status_string(tsgne.TSGNE_E_GRAPH) == b"TSGNE_E_GRAPH"
