@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "mirror", "edge_sqdist", "calibrate",
+    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "mirror", "edge_sqdist", "calibrate",
     "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
@@ -58,6 +58,9 @@ def lib():
             "oracle_mirror": (ctypes.c_int, [i32, i64, vp, vp, vp]),
             "oracle_knn_graph": (ctypes.c_int, [i32, vp, vp, i32, vp, vp, vp]),
             "oracle_shortest_path_embedding": (ctypes.c_int, [i32, vp, vp, i32, vp, dbl, vp]),
+            "oracle_kmeans": (ctypes.c_int, [i32, vp, i32, vp, i32, vp, vp]),
+            "oracle_nmi": (dbl, [i32, vp, i32, vp, i32]),
+            "oracle_aq": (dbl, [i32, vp, vp, i32, i32, dbl]),
             "oracle_edge_sqdist": (None, [i32, vp, vp, vp, i32, vp]),
             "oracle_calibrate": (None, [i32, vp, vp, dbl, vp, vp]),
             "oracle_symmetrise": (ctypes.c_int, [i32, vp, vp, vp, vp]),
@@ -139,6 +142,33 @@ def shortest_path_embedding(row_ptr, col, targets, l0: float) -> np.ndarray:
     if rc != 0:
         raise OracleError("shortest_path_embedding failed (%d)" % rc)
     return X
+
+
+def kmeans(Y, seeds, max_iter: int = 300):
+    """Labels int32[n] and the number of passes: Lloyd's k-means on the layout
+    quantised to its bounding box (section 2.5, readings in the C source)."""
+    Y = np.ascontiguousarray(Y, np.float32)
+    seeds = _i32(seeds)
+    n = Y.shape[0]
+    labels = np.zeros(n, np.int32)
+    iters = ctypes.c_int32(0)
+    rc = lib().oracle_kmeans(n, _p(Y), seeds.shape[0], _p(seeds), int(max_iter), _p(labels), ctypes.byref(iters))
+    if rc != 0:
+        raise OracleError("kmeans failed (%d)" % rc)
+    return labels, iters.value
+
+
+def nmi(a, ka: int, b, kb: int) -> float:
+    """Normalised mutual information of two labelings (section 2.5, eq. (11))."""
+    a, b = _i32(a), _i32(b)
+    return float(lib().oracle_nmi(a.shape[0], _p(a), int(ka), _p(b), int(kb)))
+
+
+def aq(Y, labels, n_labels: int, grid: int, p: float) -> float:
+    """Aesthetic quality of a layout (section 2.6, eqs. (12)-(14))."""
+    Y = np.ascontiguousarray(Y, np.float32)
+    labels = _i32(labels)
+    return float(lib().oracle_aq(Y.shape[0], _p(Y), _p(labels), int(n_labels), int(grid), float(p)))
 
 
 def mirror(row_ptr, col) -> np.ndarray:

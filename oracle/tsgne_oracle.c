@@ -536,3 +536,215 @@ void oracle_run(int32_t n, const int32_t* row_ptr, const int32_t* col, const dou
   }
   free(g);
 }
+
+/* ------------------------------------------------------------------ */
+/* Layout quality: NMI (section 2.5, eq. (11)) and AQ (section 2.6,     */
+/* eqs. (12)-(14)).                                                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Quantised layout coordinates for the clustering of section 2.5.  Reading:
+ * the paper clusters the layout with "kNN clustering" whose k is the number
+ * of graph clusters, read as k-means (Lloyd).  So that every decision of the
+ * clustering is reproducible, it runs on the layout mapped onto a 2^24 x 2^24
+ * grid over its bounding box: q = min(floor((y - lo) / (hi - lo) * 2^24),
+ * 2^24 - 1), 0 when hi == lo.  Returns ORACLE_EINVAL on a non-finite
+ * coordinate.
+ */
+static int quantise_layout(int32_t n, const float* Y, int32_t* q) {
+  for (int a = 0; a < 2; ++a) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t i = 0; i < n; ++i) {
+      const double v = (double)Y[2 * (int64_t)i + a];
+      if (!isfinite(v)) return ORACLE_EINVAL;
+      if (v < lo) lo = v;
+      if (v > hi) hi = v;
+    }
+    const double span = hi - lo;
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t u = 0;
+      if (span > 0) {
+        const double t = floor(((double)Y[2 * (int64_t)i + a] - lo) / span * 16777216.0);
+        u = t > 16777215.0 ? 16777215 : (int32_t)t;
+      }
+      q[2 * (int64_t)i + a] = u;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/*
+ * k-means (Lloyd) on the quantised layout, the clustering of the layout in
+ * section 2.5.  Readings: the initial centres are the points at the k given
+ * node indices (the caller draws them); each pass assigns every point to the
+ * nearest centre by squared Euclidean distance in FP64 (ties to the lower
+ * cluster index), stops when no label changes, and otherwise moves every
+ * non-empty cluster's centre to the mean of its points (exact integer sums,
+ * one division); an empty cluster keeps its centre.  At most max_iter
+ * passes; *iters receives the number made.
+ */
+int oracle_kmeans(int32_t n, const float* Y, int32_t k, const int32_t* seeds, int32_t max_iter, int32_t* labels,
+                  int32_t* iters) {
+  if (n < 1 || k < 1 || max_iter < 1) return ORACLE_EINVAL;
+  int32_t* q = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)n);
+  double* cx = (double*)malloc(sizeof(double) * (size_t)k);
+  double* cy = (double*)malloc(sizeof(double) * (size_t)k);
+  int64_t* sx = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int64_t* sy = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int rc = ORACLE_OK;
+  if (!q || !cx || !cy || !sx || !sy || !cnt) {
+    rc = ORACLE_ENOMEM;
+    goto done;
+  }
+  rc = quantise_layout(n, Y, q);
+  if (rc != ORACLE_OK) goto done;
+  for (int32_t c = 0; c < k; ++c) {
+    if (seeds[c] < 0 || seeds[c] >= n) {
+      rc = ORACLE_EINVAL;
+      goto done;
+    }
+    cx[c] = (double)q[2 * (int64_t)seeds[c]];
+    cy[c] = (double)q[2 * (int64_t)seeds[c] + 1];
+  }
+  for (int32_t i = 0; i < n; ++i) labels[i] = -1;
+  int32_t it = 0;
+  while (it < max_iter) {
+    ++it;
+    int64_t changed = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      const double px = (double)q[2 * (int64_t)i], py = (double)q[2 * (int64_t)i + 1];
+      int32_t best = 0;
+      double bd = INFINITY;
+      for (int32_t c = 0; c < k; ++c) {
+        const double dx = px - cx[c], dy = py - cy[c];
+        const double dist = dx * dx + dy * dy;
+        if (dist < bd) {
+          bd = dist;
+          best = c;
+        }
+      }
+      if (labels[i] != best) ++changed;
+      labels[i] = best;
+    }
+    if (changed == 0) break;
+    for (int32_t c = 0; c < k; ++c) sx[c] = sy[c] = cnt[c] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      sx[labels[i]] += q[2 * (int64_t)i];
+      sy[labels[i]] += q[2 * (int64_t)i + 1];
+      cnt[labels[i]] += 1;
+    }
+    for (int32_t c = 0; c < k; ++c) {
+      if (cnt[c] > 0) {
+        cx[c] = (double)sx[c] / (double)cnt[c];
+        cy[c] = (double)sy[c] / (double)cnt[c];
+      }
+    }
+  }
+  *iters = it;
+done:
+  free(q);
+  free(cx);
+  free(cy);
+  free(sx);
+  free(sy);
+  free(cnt);
+  return rc;
+}
+
+/*
+ * NMI of two labelings (section 2.5, eq. (11)): 2 I(A;B) / (H(A) + H(B)) with
+ * natural logarithms (the base cancels).  Readings: the paper's remark that a
+ * smaller NMI means more similar partitions is reversed in its own formula
+ * (identical partitions give 1); when both labelings have a single cluster,
+ * H(A) + H(B) = 0 and the NMI is taken as 1.  Labels lie in [0, ka) and
+ * [0, kb).  Returns NaN on a label out of range.
+ */
+double oracle_nmi(int32_t n, const int32_t* a, int32_t ka, const int32_t* b, int32_t kb) {
+  if (n < 1 || ka < 1 || kb < 1) return NAN;
+  int64_t* nij = (int64_t*)calloc((size_t)ka * (size_t)kb, sizeof(int64_t));
+  int64_t* na = (int64_t*)calloc((size_t)ka, sizeof(int64_t));
+  int64_t* nb = (int64_t*)calloc((size_t)kb, sizeof(int64_t));
+  double result = NAN;
+  if (!nij || !na || !nb) goto done;
+  for (int32_t i = 0; i < n; ++i) {
+    if (a[i] < 0 || a[i] >= ka || b[i] < 0 || b[i] >= kb) goto done;
+    nij[(int64_t)a[i] * kb + b[i]] += 1;
+    na[a[i]] += 1;
+    nb[b[i]] += 1;
+  }
+  {
+    const double N = (double)n;
+    double ha = 0, hb = 0, mi = 0;
+    for (int32_t x = 0; x < ka; ++x)
+      if (na[x] > 0) ha -= ((double)na[x] / N) * log((double)na[x] / N);
+    for (int32_t y = 0; y < kb; ++y)
+      if (nb[y] > 0) hb -= ((double)nb[y] / N) * log((double)nb[y] / N);
+    for (int32_t x = 0; x < ka; ++x)
+      for (int32_t y = 0; y < kb; ++y) {
+        const int64_t c = nij[(int64_t)x * kb + y];
+        if (c > 0) mi += ((double)c / N) * log(N * (double)c / ((double)na[x] * (double)nb[y]));
+      }
+    result = (ha + hb > 0) ? 2.0 * mi / (ha + hb) : 1.0;
+  }
+done:
+  free(nij);
+  free(na);
+  free(nb);
+  return result;
+}
+
+/*
+ * Aesthetic quality (section 2.6, eqs. (12)-(14)): the layout's bounding box
+ * is cut into grid x grid cells of width x0 = (Xmax - Xmin) / grid and height
+ * y0 = (Ymax - Ymin) / grid; a cell is good when the largest fraction of its
+ * points that share one cluster label exceeds p; AQ = good cells / grid^2.
+ * Readings: a point on the upper edge belongs to the last cell; an empty cell
+ * is not good; a degenerate axis (max == min) puts every point in its first
+ * cell.  Returns NaN on a non-finite coordinate or a label out of range.
+ */
+double oracle_aq(int32_t n, const float* Y, const int32_t* labels, int32_t n_labels, int32_t grid, double p) {
+  if (n < 1 || n_labels < 1 || grid < 1) return NAN;
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+  for (int32_t i = 0; i < n; ++i)
+    for (int a = 0; a < 2; ++a) {
+      const double v = (double)Y[2 * (int64_t)i + a];
+      if (!isfinite(v)) return NAN;
+      if (v < lo[a]) lo[a] = v;
+      if (v > hi[a]) hi[a] = v;
+    }
+  const double w[2] = {(hi[0] - lo[0]) / grid, (hi[1] - lo[1]) / grid};
+  const int64_t cells = (int64_t)grid * grid;
+  int64_t* count = (int64_t*)calloc((size_t)cells * (size_t)n_labels, sizeof(int64_t));
+  if (!count) return NAN;
+  double result = NAN;
+  for (int32_t i = 0; i < n; ++i) {
+    if (labels[i] < 0 || labels[i] >= n_labels) goto done;
+    int64_t cell[2];
+    for (int a = 0; a < 2; ++a) {
+      int64_t c = 0;
+      if (w[a] > 0) {
+        const double t = floor(((double)Y[2 * (int64_t)i + a] - lo[a]) / w[a]);
+        c = t > grid - 1 ? grid - 1 : (int64_t)t;
+      }
+      cell[a] = c;
+    }
+    count[(cell[1] * grid + cell[0]) * n_labels + labels[i]] += 1;
+  }
+  {
+    int64_t good = 0;
+    for (int64_t c = 0; c < cells; ++c) {
+      int64_t total = 0, best = 0;
+      for (int32_t l = 0; l < n_labels; ++l) {
+        const int64_t v = count[c * n_labels + l];
+        total += v;
+        if (v > best) best = v;
+      }
+      if (total > 0 && (double)best / (double)total > p) ++good;
+    }
+    result = (double)good / (double)cells;
+  }
+done:
+  free(count);
+  return result;
+}

@@ -434,3 +434,115 @@ def test_shortest_path_embedding_against_scipy(seed, n, l0):
     expect = np.where(np.isfinite(D) & (D <= l0), D, l0 + 1.0).T.astype(np.float32)
     assert np.array_equal(X, expect)
     assert np.all(X[targets, np.arange(7)] == 0)
+
+
+# ---------------------------------------------------------------------------
+# Layout quality: NMI (section 2.5, eq. (11)), k-means on the layout
+# (section 2.5, read as Lloyd from given centres), AQ (section 2.6)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,ka,kb,seed", [(50, 3, 4, 0), (1000, 10, 7, 1), (5000, 40, 40, 2), (300, 1, 5, 3)])
+def test_nmi_against_sklearn(n, ka, kb, seed):
+    from sklearn.metrics import normalized_mutual_info_score
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, ka, n).astype(np.int32)
+    b = np.where(rng.random(n) < 0.6, a % kb, rng.integers(0, kb, n)).astype(np.int32)   # correlated
+    ref = normalized_mutual_info_score(a, b, average_method="arithmetic")
+    assert abs(oracle.nmi(a, ka, b, kb) - ref) <= 1e-12
+
+
+def test_nmi_special_cases():
+    a = np.repeat(np.arange(4, dtype=np.int32), 25)
+    perm = np.array([2, 0, 3, 1], np.int32)
+    assert oracle.nmi(a, 4, perm[a], 4) == pytest.approx(1.0, abs=1e-15)      # same partition, renamed
+    x = np.arange(400, dtype=np.int32)
+    assert abs(oracle.nmi(x % 2, 2, (x // 2) % 2, 2)) <= 1e-15                # independent: I = 0
+    z = np.zeros(10, np.int32)
+    assert oracle.nmi(z, 1, z, 1) == 1.0                                       # both single-cluster
+    assert np.isnan(oracle.nmi(z, 1, np.full(10, 5, np.int32), 3))             # label out of range
+
+
+def quantised(Y):
+    # the grid the clustering runs on: 2^24 steps over each axis' range
+    Y = Y.astype(np.float64)
+    lo, hi = Y.min(0), Y.max(0)
+    q = np.floor((Y - lo) / (hi - lo) * 2.0 ** 24)
+    return np.minimum(q, 2.0 ** 24 - 1)
+
+
+def blobs(n, k, seed, spread=0.3):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-50, 50, (k, 2))
+    lab = rng.integers(0, k, n)
+    return (centres[lab] + spread * rng.standard_normal((n, 2))).astype(np.float32), lab
+
+
+@pytest.mark.parametrize("n,k,seed", [(500, 3, 0), (4000, 12, 1), (20000, 30, 2)])
+def test_kmeans_against_sklearn_lloyd(n, k, seed):
+    from sklearn.cluster import KMeans
+    Y, _ = blobs(n, k, seed, spread=2.0)
+    seeds = np.random.default_rng(seed + 7).choice(n, k, replace=False).astype(np.int32)
+    labels, iters = oracle.kmeans(Y, seeds, max_iter=300)
+    q = quantised(Y)
+    km = KMeans(n_clusters=k, init=q[seeds], n_init=1, max_iter=300, tol=0.0, algorithm="lloyd").fit(q)
+    assert np.array_equal(labels, km.labels_)
+    assert iters < 300
+
+
+def test_kmeans_fixed_point_and_hand_case():
+    Y, _ = blobs(3000, 8, 5, spread=6.0)          # overlapping blobs
+    seeds = np.arange(8, dtype=np.int32) * 100
+    labels, iters = oracle.kmeans(Y, seeds, max_iter=500)
+    assert iters < 500
+    q = quantised(Y)
+    cent = np.stack([q[labels == c].mean(0) for c in range(8)])
+    d2 = ((q[:, None, :] - cent[None]) ** 2).sum(-1)
+    assert np.array_equal(labels, d2.argmin(1))     # every point at its nearest mean
+    # hand-worked: x = 0, 1, 10, 11 from centres at the first two points:
+    # pass 1 gives [0, 1, 1, 1], pass 2 [0, 0, 1, 1], pass 3 changes nothing
+    H = np.array([[0, 0], [1, 0], [10, 0], [11, 0]], np.float32)
+    labels, iters = oracle.kmeans(H, np.array([0, 1], np.int32))
+    assert labels.tolist() == [0, 0, 1, 1] and iters == 3
+    # coincident points: every tie goes to the lower index
+    labels, iters = oracle.kmeans(np.ones((5, 2), np.float32), np.array([0, 3, 4], np.int32))
+    assert labels.tolist() == [0] * 5 and iters == 2
+    with pytest.raises(oracle.OracleError):
+        oracle.kmeans(H, np.array([0, 4], np.int32))
+
+
+def test_aq_hand_cases():
+    corners = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], np.float32)
+    lab = np.array([0, 0, 1, 1], np.int32)
+    assert oracle.aq(corners, lab, 2, 2, 0.5) == 1.0     # one point per cell
+    assert oracle.aq(corners, lab, 2, 1, 0.5) == 0.0     # one cell, half and half: not > 0.5
+    assert oracle.aq(corners, lab, 2, 1, 0.4) == 1.0
+    # x = 0..3 on a 3 x 3 grid: x = 3 lies on the upper edge and joins the last
+    # column; y = 0 for all, so only the bottom row is used
+    line = np.array([[0, 0], [1, 0], [2, 0], [3, 0]], np.float32)
+    # cells: col 0 {0}, col 1 {1}, col 2 {2, 3}; labels 0, 1, 0, 1 -> col 2 is 1:1
+    assert oracle.aq(line, np.array([0, 1, 0, 1], np.int32), 2, 3, 0.5) == pytest.approx(2 / 9)
+    # 3 x 3: a 9-point pattern with two mixed cells
+    pts, labs = [], []
+    for cx in range(3):
+        for cy in range(3):
+            for r in range(3):
+                pts.append([cx + 0.2 + 0.3 * r, cy + 0.5])
+                labs.append(0 if (cx, cy) not in ((1, 1), (2, 0)) else r % 2)
+    pts = np.array(pts + [[0, 0], [3, 3]], np.float32)          # corners fix the box to [0, 3]^2
+    labs = np.array(labs + [0, 0], np.int32)
+    # mixed cells hold labels (0, 1, 0): fraction 2/3 -> good at p = 0.5, not at p = 0.7
+    assert oracle.aq(pts, labs, 2, 3, 0.5) == 1.0
+    assert oracle.aq(pts, labs, 2, 3, 0.7) == pytest.approx(7 / 9)
+
+
+def test_aq_invariants():
+    Y, lab = blobs(2000, 5, 11, spread=3.0)
+    lab = lab.astype(np.int32)
+    a = oracle.aq(Y, lab, 5, 10, 0.6)
+    assert 0.0 <= a <= 1.0
+    assert oracle.aq(Y * np.float32(4.0), lab, 5, 10, 0.6) == a            # exact rescaling
+    one = np.zeros_like(lab)
+    q = np.floor((Y.astype(np.float64) - Y.min(0)) / ((Y.max(0) - Y.min(0)) / 10.0))
+    occupied = len({(min(int(x), 9), min(int(y), 9)) for x, y in q})
+    assert oracle.aq(Y, one, 1, 10, 0.99) == pytest.approx(occupied / 100)  # single label: every occupied cell
+    assert oracle.aq(Y, lab, 5, 10, 1.0) == 0.0                             # fraction never exceeds 1
