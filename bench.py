@@ -307,6 +307,31 @@ def run_sparse(args) -> int:
     return 0
 
 
+AQ_GRID, AQ_P = 20, 0.5
+
+
+def layout_quality(Y, gi, dev, stream):
+    """NMI (section 2.5) of the final layout's k-means clusters against the planted
+    communities, with k = the number of communities, and AQ (section 2.6) of the
+    layout coloured by the communities; computed after the timed region."""
+    import numpy as np
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    comm = int(gi.labels.max()) + 1
+    seeds = np.random.default_rng(synth.MASTER_SEED + 11).choice(gi.n, comm, replace=False).astype(np.int32)
+    truth = torch.from_numpy(gi.labels.astype(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    labels, passes = tsgne.tsgne_kmeans(Y, torch.from_numpy(seeds).to(dev), 300, stream)
+    nmi = tsgne.tsgne_nmi(truth, comm, labels, comm, stream)
+    aq = tsgne.tsgne_aq(Y, truth, comm, AQ_GRID, AQ_P, stream)
+    seconds = time.perf_counter() - t0
+    return {"nmi": nmi, "aq": aq, "clusters": comm, "kmeans_passes": passes, "aq_grid": AQ_GRID, "aq_p": AQ_P,
+            "labels": "planted communities", "seconds": seconds}
+
+
 def run_sp(args) -> int:
     """The ShortestPath embedding (section 2.3, eq. (8)) of the 300,000-node,
     1,000,000-edge graph with 128 seeded random targets and l0 = sqrt(|E|)."""
@@ -456,6 +481,7 @@ def main() -> int:
     n = gi.n
     pairs_per_iter = n * (n - 1)
     value = args.steps * n_iter * pairs_per_iter / elapsed
+    quality = layout_quality(Y, gi, dev, stream)
     rep_ms = sum(t["repulsion"][0] for t in timings)
     rep_launches = sum(t["repulsion"][1] for t in timings)
     avg_rep_s = rep_ms / max(rep_launches, 1) / 1e3
@@ -499,6 +525,7 @@ def main() -> int:
         },
         "phase_avg_ms": phase_avg_ms,
         "final_kl": kls[-1] if kls else None,
+        "quality": quality,
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (~%.0f s)" % args.cpu_seconds)

@@ -150,6 +150,62 @@ TSGNE_API tsgne_status tsgne_shortest_path_embedding(int32_t n, int64_t nnz, con
                                                      double l0, float* X_d, int32_t* levels_out, void* stream);
 
 /*
+ * Layout quality (sections 2.5-2.6).  The three calls below are
+ * synchronising and leave every input unchanged.
+ *
+ * tsgne_kmeans: the clustering of the layout used for the NMI of section
+ * 2.5, which the paper calls kNN clustering with k set to the number of graph
+ * clusters; read as Lloyd's k-means.  The layout is mapped onto a 2^24 x 2^24
+ * grid over its bounding box (q = min(floor((y - lo) / (hi - lo) * 2^24),
+ * 2^24 - 1), 0 on a flat axis) so that every decision is reproducible: each
+ * pass assigns every point to the nearest centre (squared distance in FP64,
+ * ties to the lower index) and, unless no label changed, moves each
+ * non-empty cluster's centre to the exact mean of its points; an empty
+ * cluster keeps its centre.
+ *   n, Y_d      -- float32[n][2] layout (device), n >= 1
+ *   k           -- 1 .. 1024 clusters
+ *   seeds_d     -- int32[k] (device): the initial centres are the points at
+ *                  these node indices (the caller draws them)
+ *   max_iter    -- at most this many passes (>= 1)
+ *   labels_d    -- int32[n] (device, written): cluster of each node
+ *   iters_out   -- nullable: passes made (the last one changed nothing,
+ *                  unless max_iter was reached)
+ * Errors: E_INVAL (sizes, a seed outside [0, n)), E_NONFINITE (a
+ * non-finite coordinate), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_kmeans(int32_t n, const float* Y_d, int32_t k, const int32_t* seeds_d, int32_t max_iter,
+                                    int32_t* labels_d, int32_t* iters_out, void* stream);
+
+/*
+ * tsgne_nmi: normalised mutual information of two labelings of n nodes
+ * (section 2.5, eq. (11)): 2 I(A;B) / (H(A) + H(B)), natural logarithms;
+ * identical partitions give 1, and two single-cluster labelings give 1.
+ *   a_d, b_d -- int32[n] (device), labels in [0, ka) and [0, kb)
+ *   ka, kb   -- label counts, ka * kb <= 2^26
+ *   nmi_out  -- host double (written)
+ * Errors: E_INVAL (sizes, a label out of range), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_nmi(int32_t n, const int32_t* a_d, int32_t ka, const int32_t* b_d, int32_t kb,
+                                 double* nmi_out, void* stream);
+
+/*
+ * tsgne_aq: aesthetic quality of a layout (section 2.6, eqs. (12)-(14)): the
+ * bounding box is cut into grid x grid cells of width (Xmax - Xmin) / grid
+ * and height (Ymax - Ymin) / grid; a cell is good when the largest fraction
+ * of its points sharing one label exceeds p; AQ = good cells / grid^2.
+ * Readings: points on the upper edge belong to the last cell, an empty cell
+ * is not good, a flat axis puts every point in its first cell.
+ *   Y_d      -- float32[n][2] layout (device)
+ *   labels_d -- int32[n] (device) in [0, n_labels) (e.g. graph communities)
+ *   grid     -- 1 .. 4096, grid^2 * n_labels <= 2^28
+ *   p        -- threshold
+ *   aq_out   -- host double (written)
+ * Errors: E_INVAL, E_NONFINITE, E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_aq(int32_t n, const float* Y_d, const int32_t* labels_d, int32_t n_labels, int32_t grid,
+                                double p, double* aq_out, void* stream);
+
+/*
  * Builds the joint affinities P of eq. (3) from the conditional affinities of
  * eq. (2) over each node's graph neighbours (section 2.2), with the bandwidth
  * of each row set by bisection so that its perplexity equals `perplexity`

@@ -35,7 +35,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 # every symbol include/tsgne.h declares
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
-    "tsgne_shortest_path_embedding", "tsgne_build_P",
+    "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
@@ -128,6 +128,9 @@ def lib():
             "tsgne_knn_graph": (st, [i32, i64, vp, vp, i32, vp, vp, i64, ctypes.POINTER(i64), vp]),
             "tsgne_shortest_path_embedding": (st, [i32, i64, vp, vp, i32, vp, ctypes.c_double, vp,
                                                    ctypes.POINTER(i32), vp]),
+            "tsgne_kmeans": (st, [i32, vp, i32, vp, i32, vp, ctypes.POINTER(i32), vp]),
+            "tsgne_nmi": (st, [i32, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_aq": (st, [i32, vp, vp, i32, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -251,6 +254,43 @@ def tsgne_shortest_path_embedding(row_ptr, col, targets, l0: float = -1.0, strea
                                                d, _ptr(targets), float(l0), _ptr(X), ctypes.byref(levels),
                                                _stream(stream)))
     return X, levels.value
+
+
+def tsgne_kmeans(Y, seeds, max_iter: int = 300, stream=None):
+    """Layout clustering of section 2.5 (Lloyd's k-means from the given seed nodes on
+    the quantised layout): returns (labels int32 device tensor, passes made)."""
+    import torch
+    _require(Y, torch.float32, name="Y")
+    _require(seeds, torch.int32, name="seeds")
+    n = Y.shape[0]
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=Y.device)
+    iters = ctypes.c_int32(0)
+    _check(lib().tsgne_kmeans(n, _ptr(Y), seeds.shape[0], _ptr(seeds), int(max_iter), _ptr(labels),
+                              ctypes.byref(iters), _stream(stream)))
+    return labels[:n], iters.value
+
+
+def tsgne_nmi(a, ka: int, b, kb: int, stream=None) -> float:
+    """NMI of two device labelings (section 2.5, eq. (11))."""
+    import torch
+    _require(a, torch.int32, name="a")
+    _require(b, torch.int32, name="b")
+    if a.shape != b.shape:
+        raise ValueError("labelings differ in length")
+    out = ctypes.c_double(0)
+    _check(lib().tsgne_nmi(a.shape[0], _ptr(a), int(ka), _ptr(b), int(kb), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def tsgne_aq(Y, labels, n_labels: int, grid: int, p: float, stream=None) -> float:
+    """Aesthetic quality of a device layout (section 2.6, eqs. (12)-(14))."""
+    import torch
+    _require(Y, torch.float32, name="Y")
+    _require(labels, torch.int32, name="labels")
+    out = ctypes.c_double(0)
+    _check(lib().tsgne_aq(Y.shape[0], _ptr(Y), _ptr(labels), int(n_labels), int(grid), float(p), ctypes.byref(out),
+                          _stream(stream)))
+    return out.value
 
 
 class Graph:
