@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "mirror", "edge_sqdist", "calibrate",
+    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "philox4x32_10", "walk_P", "mirror", "edge_sqdist", "calibrate",
     "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
@@ -59,6 +59,8 @@ def lib():
             "oracle_knn_graph": (ctypes.c_int, [i32, vp, vp, i32, vp, vp, vp]),
             "oracle_shortest_path_embedding": (ctypes.c_int, [i32, vp, vp, i32, vp, dbl, vp]),
             "oracle_kmeans": (ctypes.c_int, [i32, vp, i32, vp, i32, vp, vp]),
+            "oracle_philox4x32_10": (None, [vp, vp, vp]),
+            "oracle_walk_P": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp, vp, vp, vp]),
             "oracle_nmi": (dbl, [i32, vp, i32, vp, i32]),
             "oracle_aq": (dbl, [i32, vp, vp, i32, i32, dbl]),
             "oracle_edge_sqdist": (None, [i32, vp, vp, vp, i32, vp]),
@@ -169,6 +171,32 @@ def aq(Y, labels, n_labels: int, grid: int, p: float) -> float:
     Y = np.ascontiguousarray(Y, np.float32)
     labels = _i32(labels)
     return float(lib().oracle_aq(Y.shape[0], _p(Y), _p(labels), int(n_labels), int(grid), float(p)))
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block (Salmon et al. 2011): uint32[4] from a uint32[4] counter and uint32[2] key."""
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().oracle_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def walk_P(row_ptr, col, X, walks: int, length: int, seed: int):
+    """(row_ptr, col, P float32) of the random-walk P of section 2.1 (readings in the C source)."""
+    row_ptr, col = _i32(row_ptr), _i32(col)
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = row_ptr.shape[0] - 1, X.shape[1]
+    cap = max(2 * n * int(walks), 1)
+    orp = np.zeros(n + 1, np.int32)
+    ocol = np.zeros(cap, np.int32)
+    P = np.zeros(cap, np.float32)
+    nnz = ctypes.c_int64(0)
+    rc = lib().oracle_walk_P(n, _p(row_ptr), _p(col), _p(X), d, int(walks), int(length), ctypes.c_uint64(seed),
+                             _p(orp), _p(ocol), _p(P), ctypes.byref(nnz))
+    if rc != 0:
+        raise OracleError("walk_P failed (%d)" % rc)
+    return orp, ocol[: nnz.value].copy(), P[: nnz.value].copy()
 
 
 def mirror(row_ptr, col) -> np.ndarray:

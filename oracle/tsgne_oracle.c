@@ -748,3 +748,136 @@ done:
   free(count);
   return result;
 }
+
+/* ------------------------------------------------------------------ */
+/* Random-walk P (section 2.1, the approximation of P by random walks). */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds of the 4x32 Philox S-box with
+ * multipliers 0xD2511F53 and 0xCD9E8D57, the key advanced by the Weyl
+ * constants 0x9E3779B9 and 0xBB67AE85 between rounds.
+ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c[0];
+  out[1] = c[1];
+  out[2] = c[2];
+  out[3] = c[3];
+}
+
+/* The uniform draw of step s of walk w from node i: 53 bits of Philox output
+ * for counter (i, w, s, 0) and the 64-bit seed as key, in [0, 1). */
+static double walk_uniform(uint64_t seed, int32_t i, int32_t w, int32_t s) {
+  const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)w, (uint32_t)s, 0u};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  oracle_philox4x32_10(ctr, key, x);
+  return ((double)x[0] * 2097152.0 + (double)(x[1] >> 11)) * 0x1p-53;
+}
+
+static int cmp_u64(const void* a, const void* b) {
+  const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * P from random walks (section 2.1).  Readings: walks run on the given graph
+ * (its CSR, canonical and symmetric); from node u the next node is the
+ * neighbour v with probability proportional to exp(-||x_u - x_v||^2) (the
+ * printed exponent lacks its minus sign), evaluated as exp(-(D_uv - D_min,u))
+ * with D summed over the coordinates in order in FP64; the neighbour is the
+ * first CSR entry whose running weight sum exceeds u * (row total), u the
+ * uniform of walk_uniform (the last entry if none does).  Each node starts
+ * `walks` walks of `length` steps (a walk from an isolated node stays put);
+ * p_{j|i} = (walks from i ending at j != i) / walks, and symmetrising as in
+ * eq. (3) with S the total mass gives P_ij = (c_ij + c_ji) / (2 M), M the
+ * walks that do not end where they started.  The support (pairs with
+ * c_ij + c_ji > 0) is returned as a canonical symmetric CSR with P aligned
+ * with col; out_col and P need room for 2 n walks entries.
+ */
+int oracle_walk_P(int32_t n, const int32_t* row_ptr, const int32_t* col, const float* X, int32_t d, int32_t walks,
+                  int32_t length, uint64_t seed, int32_t* out_row_ptr, int32_t* out_col, float* P, int64_t* out_nnz) {
+  if (n < 1 || d < 1 || walks < 1 || length < 1) return ORACLE_EINVAL;
+  const int64_t nnz = row_ptr[n];
+  double* C = (double*)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (size_t)n * (size_t)walks);
+  if (!C || !keys) {
+    free(C);
+    free(keys);
+    return ORACLE_ENOMEM;
+  }
+  /* running transition weights per row */
+  for (int32_t u = 0; u < n; ++u) {
+    double dmin = INFINITY;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      double D = 0;
+      for (int32_t k = 0; k < d; ++k) {
+        const double t = (double)X[(int64_t)u * d + k] - (double)X[(int64_t)col[e] * d + k];
+        D += t * t;
+      }
+      C[e] = D;
+      if (D < dmin) dmin = D;
+    }
+    double run = 0;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      run += exp(-(C[e] - dmin));
+      C[e] = run;
+    }
+  }
+  int64_t m = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t w = 0; w < walks; ++w) {
+      int32_t u = i;
+      for (int32_t s = 0; s < length; ++s) {
+        const int64_t a = row_ptr[u], b = row_ptr[u + 1];
+        if (a == b) break;
+        const double r = walk_uniform(seed, i, w, s) * C[b - 1];
+        int64_t pick = b - 1;
+        for (int64_t e = a; e < b; ++e)
+          if (C[e] > r) {
+            pick = e;
+            break;
+          }
+        u = col[pick];
+      }
+      if (u != i) {
+        keys[m++] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)u;
+        keys[m++] = ((uint64_t)(uint32_t)u << 32) | (uint32_t)i;
+      }
+    }
+  }
+  qsort(keys, (size_t)m, sizeof(uint64_t), cmp_u64);
+  int64_t out = 0;
+  for (int32_t r = 0; r <= n; ++r) out_row_ptr[r] = 0;
+  for (int64_t a = 0; a < m;) {
+    int64_t b = a;
+    while (b < m && keys[b] == keys[a]) ++b;
+    const int32_t row = (int32_t)(keys[a] >> 32);
+    out_col[out] = (int32_t)(keys[a] & 0xffffffffu);
+    P[out] = (float)((double)(b - a) / (double)m); /* (c_ij + c_ji) / (2 M), m = 2 M */
+    out_row_ptr[row + 1] += 1;
+    ++out;
+    a = b;
+  }
+  for (int32_t r = 0; r < n; ++r) out_row_ptr[r + 1] += out_row_ptr[r];
+  *out_nnz = out;
+  free(C);
+  free(keys);
+  return ORACLE_OK;
+}

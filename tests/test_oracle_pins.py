@@ -546,3 +546,84 @@ def test_aq_invariants():
     occupied = len({(min(int(x), 9), min(int(y), 9)) for x, y in q})
     assert oracle.aq(Y, one, 1, 10, 0.99) == pytest.approx(occupied / 100)  # single label: every occupied cell
     assert oracle.aq(Y, lab, 5, 10, 1.0) == 0.0                             # fraction never exceeds 1
+
+
+# ---------------------------------------------------------------------------
+# Random-walk P (section 2.1) and its generator
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    kat = json.load(open(os.path.join(os.path.dirname(GOLDEN), "philox4x32_10_kat.json")))
+    for case in kat["cases"]:
+        out = oracle.philox4x32_10([int(x, 16) for x in case["ctr"]], [int(x, 16) for x in case["key"]])
+        assert [int(x) for x in out] == [int(x, 16) for x in case["out"]]
+
+
+def transition_matrix(rp, col, X):
+    # exp(-||x_u - x_v||^2) over each node's neighbours, normalised per row
+    n = rp.shape[0] - 1
+    T = np.zeros((n, n))
+    Xd = X.astype(np.float64)
+    for u in range(n):
+        nb = col[rp[u]:rp[u + 1]]
+        if len(nb) == 0:
+            T[u, u] = 1.0               # a walk from an isolated node stays put
+            continue
+        D = ((Xd[u] - Xd[nb]) ** 2).sum(1)
+        w = np.exp(-(D - D.min()))
+        T[u, nb] = w / w.sum()
+    return T
+
+
+def walk_frequencies(rp, col, X, walks, length, seed):
+    orp, ocol, P = oracle.walk_P(rp, col, X, walks, length, seed)
+    n = rp.shape[0] - 1
+    dense = np.zeros((n, n))
+    for i in range(n):
+        dense[i, ocol[orp[i]:orp[i + 1]]] = P[orp[i]:orp[i + 1]]
+    return dense
+
+
+@pytest.mark.parametrize("length", [1, 2, 3])
+def test_walk_P_converges_to_transition_powers(length):
+    # a small graph with distinct edge weights; many walks per node
+    rng = np.random.default_rng(length)
+    n = 9
+    edges = np.array([[0, 1], [1, 2], [2, 3], [3, 0], [1, 4], [4, 5], [5, 6], [6, 4], [2, 7]], np.int32)
+    rp, col = oracle.csr_from_edges(n, edges)          # node 8 isolated
+    X = rng.standard_normal((n, 3)).astype(np.float32)
+    walks = 40000
+    dense = walk_frequencies(rp, col, X, walks, length, 1234 + length)
+    T = transition_matrix(rp, col, X)
+    Tl = np.linalg.matrix_power(T, length)
+    c = Tl.copy()
+    np.fill_diagonal(c, 0.0)                            # walks ending where they started do not count
+    M = c.sum()                                         # expected non-returning walks per (walk index)
+    expect = (c + c.T) / (2 * M)
+    # binomial noise of a pair count over n * walks walks
+    sigma = np.sqrt(np.maximum(expect * (1 - expect), 1e-12) / (n * walks)) * 2 + 1e-7
+    assert np.all(np.abs(dense - expect) <= 6 * sigma)
+    assert np.all(dense[8] == 0) and np.all(dense[:, 8] == 0)
+
+
+def test_walk_P_invariants():
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    gi = synth.small_sbm(400, 4, 3.0, 6, 21)
+    rp, col = oracle.csr_from_edges(gi.n, gi.edges)
+    orp, ocol, P = oracle.walk_P(rp, col, gi.X, 20, 4, 99)
+    n = gi.n
+    dense = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(orp))
+    dense[rows, ocol] = P
+    assert np.array_equal(dense, dense.T)                              # symmetric, bitwise
+    assert abs(P.astype(np.float64).sum() - 1.0) <= 1e-6
+    assert np.all(np.diff(orp) >= 0) and all(np.all(np.diff(ocol[orp[i]:orp[i + 1]]) > 0) for i in range(n))
+    assert np.all(ocol != rows)                                        # no diagonal
+    A = coo_matrix((np.ones(len(col)), (np.repeat(np.arange(n), np.diff(rp)), col)), shape=(n, n))
+    hops = shortest_path(A, unweighted=True)
+    assert np.all(hops[rows, ocol] <= 4)                                # within `length` hops
+    again = oracle.walk_P(rp, col, gi.X, 20, 4, 99)
+    assert np.array_equal(again[1], ocol) and np.array_equal(again[2], P)
+    other = oracle.walk_P(rp, col, gi.X, 20, 4, 100)
+    assert not (len(other[1]) == len(ocol) and np.array_equal(other[1], ocol) and np.array_equal(other[2], P))
