@@ -230,6 +230,32 @@ TSGNE_API tsgne_status tsgne_aq(int32_t n, const float* Y_d, const int32_t* labe
 TSGNE_API tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d, const float* X_d,
                            int32_t d, float perplexity, void* stream, tsgne_graph** out);
 
+/*
+ * The approximation of P by random walks of section 2.1, as an alternative to
+ * tsgne_build_P: each node starts `walks` walks of `length` steps on G; a step
+ * from u goes to the neighbour v with probability proportional to
+ * exp(-||x_u - x_v||^2) (read with the minus sign the printed formula lacks;
+ * evaluated as exp(-(D_uv - D_min,u)) with D in FP64); p_{j|i} = (walks from
+ * i ending at j != i) / walks, and symmetrising as in eq. (3) with the total
+ * mass gives P_ij = (c_ij + c_ji) / (2 M), M = walks that do not end at their
+ * start.  The returned graph's CSR is the support of the walks (pairs with
+ * c_ij + c_ji > 0, canonical and symmetric; at most `length` hops apart) and
+ * can be used with every call that takes a tsgne_graph; beta is zero.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011) with counter
+ * (node, walk, step, 0) and key (seed low 32 bits, seed high 32 bits); the
+ * uniform is (x0 * 2^21 + (x1 >> 11)) * 2^-53, and the step takes the first
+ * CSR entry whose running weight exceeds uniform * row total (the last entry
+ * if none does).  A walk from an isolated node stays put.
+ *   n, nnz, row_ptr_d, col_d, X_d, d -- as for tsgne_build_P
+ *   walks  -- walks per node, >= 1, with 2 * n * walks < 2^31
+ *   length -- steps per walk, 1 .. 4096
+ *   seed   -- Philox key
+ * Synchronising.  Errors: E_INVAL, E_GRAPH (input CSR), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d,
+                                           const float* X_d, int32_t d, int32_t walks, int32_t length, uint64_t seed,
+                                           void* stream, tsgne_graph** out);
+
 /* Releases a graph and all device memory it holds.  NULL is accepted. */
 TSGNE_API tsgne_status tsgne_graph_free(tsgne_graph* g);
 

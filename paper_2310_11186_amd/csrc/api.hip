@@ -87,6 +87,8 @@ void free_workspace(Workspace& ws) {
 
 void timer_destroy(PhaseTimer& t);
 
+}  // namespace
+
 void free_graph(tsgne_graph* g) {
   if (!g) return;
   int cur = 0;
@@ -104,6 +106,8 @@ void free_graph(tsgne_graph* g) {
   (void)hipSetDevice(cur);
   delete g;
 }
+
+namespace {
 
 
 // --- phase timing -----------------------------------------------------------
@@ -178,6 +182,84 @@ struct Timed {
 };
 
 }  // namespace
+
+tsgne_status graph_structure(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d, hipStream_t s,
+                             tsgne_graph** out) {
+  *out = nullptr;
+  tsgne_graph* g = new (std::nothrow) tsgne_graph();
+  if (!g) return fail(TSGNE_E_NOMEM, "host allocation failed");
+  g->n = n;
+  g->nnz = nnz;
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return fail(TSGNE_E_DEVICE, "no HIP device");
+  }
+  struct Cleanup {
+    tsgne_graph* g;
+    ~Cleanup() { free_graph(g); }
+  } guard{g};
+
+  uint32_t* err = nullptr;
+  int32_t* counters = nullptr;
+  int2* partial = nullptr;
+  struct Scratch {
+    uint32_t*& err;
+    int32_t*& counters;
+    int2*& partial;
+    ~Scratch() {
+      dfree(err);
+      dfree(counters);
+      dfree(partial);
+    }
+  } scratch{err, counters, partial};
+
+  const int32_t heavy_cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
+  TSGNE_HIP(dalloc(&g->row_ptr, (size_t)n + 1), "allocate row_ptr");
+  TSGNE_HIP(dalloc(&g->col, (size_t)nnz), "allocate col");
+  TSGNE_HIP(dalloc(&g->mirror, (size_t)nnz), "allocate mirror");
+  TSGNE_HIP(dalloc(&g->row_of, (size_t)nnz), "allocate row_of");
+  TSGNE_HIP(dalloc(&g->P, (size_t)nnz), "allocate P");
+  TSGNE_HIP(dalloc(&g->beta, (size_t)n), "allocate beta");
+  TSGNE_HIP(dalloc(&g->heavy, (size_t)heavy_cap), "allocate heavy rows");
+  TSGNE_HIP(dalloc(&err, 1), "allocate error word");
+  TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
+  TSGNE_HIP(dalloc(&partial, (size_t)row_check_blocks(n)), "allocate row counts");
+
+  TSGNE_HIP(hipMemcpyAsync(g->row_ptr, row_ptr_d, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s),
+            "copy row_ptr");
+  if (nnz > 0)
+    TSGNE_HIP(hipMemcpyAsync(g->col, col_d, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s), "copy col");
+  TSGNE_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s), "clear error word");
+  TSGNE_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s), "clear counters");
+
+  // 1. row_ptr must be valid before any kernel indexes col with it.
+  TSGNE_HIP(launch_check_rows(g->row_ptr, n, nnz, kHeavyDegree, err, counters, partial, g->heavy, nullptr, heavy_cap, s),
+            "launch row check");
+  uint32_t host_err = 0;
+  int32_t host_counters[2] = {0, 0};
+  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
+  TSGNE_HIP(hipMemcpyAsync(host_counters, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "read counters");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise row check");
+  if (host_err) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
+  g->nonisolated = host_counters[0];
+  g->n_heavy = std::min(host_counters[1], heavy_cap);
+
+  // 2. Column checks, symmetry, mirror index.
+  TSGNE_HIP(launch_mirror(g->row_ptr, g->col, n, nnz, g->mirror, g->row_of, err, s), "launch mirror");
+  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise CSR check");
+  if (host_err) {
+    std::string why = "CSR is not canonical/symmetric:";
+    if (host_err & kErrColRange) why += " column outside [0, n);";
+    if (host_err & kErrSelfLoop) why += " self-loop;";
+    if (host_err & kErrOrder) why += " columns not strictly ascending;";
+    if (host_err & kErrAsym) why += " entry (i,j) without (j,i);";
+    return fail(TSGNE_E_GRAPH, why);
+  }
+  guard.g = nullptr;
+  *out = g;
+  return TSGNE_OK;
+}
 
 tsgne_status validate_params(const tsgne_params* p) {
   if (!std::isfinite(p->early_exaggeration) || p->early_exaggeration <= 0.f)
@@ -377,88 +459,29 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
   if (!row_ptr_d || !X_d || (nnz > 0 && !col_d)) return fail(TSGNE_E_INVAL, "null pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
-  tsgne_graph* g = new (std::nothrow) tsgne_graph();
-  if (!g) return fail(TSGNE_E_NOMEM, "host allocation failed");
-  g->n = n;
-  g->nnz = nnz;
-  g->d = d;
-  g->perplexity = perplexity;
-  if (hipGetDevice(&g->device) != hipSuccess) {
-    delete g;
-    return fail(TSGNE_E_DEVICE, "no HIP device");
-  }
+  tsgne_graph* g = nullptr;
+  if (tsgne_status st = graph_structure(n, nnz, row_ptr_d, col_d, s, &g)) return st;
   struct Cleanup {
     tsgne_graph* g;
     ~Cleanup() { free_graph(g); }
   } guard{g};
+  g->d = d;
+  g->perplexity = perplexity;
 
-  uint32_t* err = nullptr;
-  int32_t* counters = nullptr;
-  int2* partial = nullptr;
   double* D = nullptr;
   double* pcond = nullptr;
   struct Scratch {
-    uint32_t*& err;
-    int32_t*& counters;
-    int2*& partial;
     double*& D;
     double*& pcond;
     ~Scratch() {
-      dfree(err);
-      dfree(counters);
-      dfree(partial);
       dfree(D);
       dfree(pcond);
     }
-  } scratch{err, counters, partial, D, pcond};
-
-  const int32_t heavy_cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
-  TSGNE_HIP(dalloc(&g->row_ptr, (size_t)n + 1), "allocate row_ptr");
-  TSGNE_HIP(dalloc(&g->col, (size_t)nnz), "allocate col");
-  TSGNE_HIP(dalloc(&g->mirror, (size_t)nnz), "allocate mirror");
-  TSGNE_HIP(dalloc(&g->row_of, (size_t)nnz), "allocate row_of");
-  TSGNE_HIP(dalloc(&g->P, (size_t)nnz), "allocate P");
-  TSGNE_HIP(dalloc(&g->beta, (size_t)n), "allocate beta");
-  TSGNE_HIP(dalloc(&g->heavy, (size_t)heavy_cap), "allocate heavy rows");
-  TSGNE_HIP(dalloc(&err, 1), "allocate error word");
-  TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
-  TSGNE_HIP(dalloc(&partial, (size_t)row_check_blocks(n)), "allocate row counts");
+  } scratch{D, pcond};
   TSGNE_HIP(dalloc(&D, (size_t)nnz), "allocate distances");
   TSGNE_HIP(dalloc(&pcond, (size_t)nnz), "allocate conditional affinities");
 
-  TSGNE_HIP(hipMemcpyAsync(g->row_ptr, row_ptr_d, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s),
-            "copy row_ptr");
-  if (nnz > 0)
-    TSGNE_HIP(hipMemcpyAsync(g->col, col_d, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s), "copy col");
-  TSGNE_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s), "clear error word");
-  TSGNE_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s), "clear counters");
-
-  // 1. row_ptr must be valid before any kernel indexes col with it.
-  TSGNE_HIP(launch_check_rows(g->row_ptr, n, nnz, kHeavyDegree, err, counters, partial, g->heavy, nullptr, heavy_cap, s),
-            "launch row check");
-  uint32_t host_err = 0;
-  int32_t host_counters[2] = {0, 0};
-  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
-  TSGNE_HIP(hipMemcpyAsync(host_counters, counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s), "read counters");
-  TSGNE_HIP(hipStreamSynchronize(s), "synchronise row check");
-  if (host_err) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
-  g->nonisolated = host_counters[0];
-  g->n_heavy = std::min(host_counters[1], heavy_cap);
-
-  // 2. Column checks, symmetry, mirror index.
-  TSGNE_HIP(launch_mirror(g->row_ptr, g->col, n, nnz, g->mirror, g->row_of, err, s), "launch mirror");
-  TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
-  TSGNE_HIP(hipStreamSynchronize(s), "synchronise CSR check");
-  if (host_err) {
-    std::string why = "CSR is not canonical/symmetric:";
-    if (host_err & kErrColRange) why += " column outside [0, n);";
-    if (host_err & kErrSelfLoop) why += " self-loop;";
-    if (host_err & kErrOrder) why += " columns not strictly ascending;";
-    if (host_err & kErrAsym) why += " entry (i,j) without (j,i);";
-    return fail(TSGNE_E_GRAPH, why);
-  }
-
-  // 3. Distances, calibration, symmetrisation.
+  // Distances, calibration, symmetrisation.
   TSGNE_HIP(launch_sqdist(g->row_of, g->col, nnz, X_d, d, D, s), "launch distances");
   TSGNE_HIP(launch_calibrate(g->row_ptr, n, g->heavy, g->n_heavy, D, (double)perplexity, pcond, g->beta, s),
             "launch calibration");

@@ -205,13 +205,22 @@ struct DeviceGuard {
 };
 
 tsgne_status validate_params(const tsgne_params* p);
+// A graph with its CSR copied from the caller's device buffers, checked
+// (canonical and symmetric, E_GRAPH otherwise), with mirror, row_of, the
+// heavy-row list and the non-isolated count; P and beta allocated, not
+// filled.  Synchronising.
+tsgne_status graph_structure(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d, hipStream_t s,
+                             tsgne_graph** out);
+void free_graph(tsgne_graph* g);
 // Checks on the device that (row_ptr, col) is a canonical symmetric CSR
 // (synchronising; E_GRAPH otherwise).
 tsgne_status validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, hipStream_t s);
-// The same in caller-provided device scratch of validate_csr_bytes(n, nnz).
+// The same in caller-provided device scratch of validate_csr_bytes(n, nnz);
+// *row_of_out (nullable) then points at the row of every entry, inside the
+// scratch.
 size_t validate_csr_bytes(int32_t n, int64_t nnz);
 tsgne_status validate_csr_in(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, void* scratch,
-                             hipStream_t s);
+                             hipStream_t s, int32_t** row_of_out = nullptr);
 float effective_eta(const tsgne_graph* g, const tsgne_params* p);
 tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p);
 

@@ -162,7 +162,7 @@ tsgne_status validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const 
 // validate_csr_bytes(n, nnz): error word, counters, per-block row counts,
 // mirror, row index.
 tsgne_status validate_csr_in(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, void* scratch,
-                             hipStream_t s) {
+                             hipStream_t s, int32_t** row_of_out) {
   const int64_t blocks = row_check_blocks(n);
   int32_t* const buf = static_cast<int32_t*>(scratch);
   uint32_t* const err = reinterpret_cast<uint32_t*>(buf);
@@ -180,6 +180,7 @@ tsgne_status validate_csr_in(int32_t n, int64_t nnz, const int32_t* row_ptr, con
   TSGNE_HIP(hipStreamSynchronize(s), "synchronise CSR check");
   if (host_err & kErrRowPtr) return fail(TSGNE_E_GRAPH, "row_ptr is not nondecreasing from 0 to nnz");
   if (host_err) return fail(TSGNE_E_GRAPH, "CSR is not canonical and symmetric");
+  if (row_of_out) *row_of_out = row_of;
   return TSGNE_OK;
 }
 

@@ -36,6 +36,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
+    "tsgne_build_P_walks",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
@@ -131,6 +132,8 @@ def lib():
             "tsgne_kmeans": (st, [i32, vp, i32, vp, i32, vp, ctypes.POINTER(i32), vp]),
             "tsgne_nmi": (st, [i32, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), vp]),
             "tsgne_aq": (st, [i32, vp, vp, i32, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_build_P_walks": (st, [i32, i64, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp,
+                                         ctypes.POINTER(vp)]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -356,6 +359,22 @@ def tsgne_build_P(row_ptr, col, X, perplexity: float, stream=None) -> Graph:
     h = ctypes.c_void_p(None)
     _check(lib().tsgne_build_P(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, _ptr(X),
                                X.shape[1], float(perplexity), _stream(stream), ctypes.byref(h)))
+    return Graph(h.value)
+
+
+def tsgne_build_P_walks(row_ptr, col, X, walks: int, length: int, seed: int, stream=None) -> Graph:
+    """P from random walks on the device CSR (section 2.1); the graph's CSR is the walks' support."""
+    import torch
+    _require(row_ptr, torch.int32, name="row_ptr")
+    _require(col, torch.int32, name="col")
+    _require(X, torch.float32, name="X")
+    n = row_ptr.shape[0] - 1
+    if X.dim() != 2 or X.shape[0] != n:
+        raise ValueError("X must be [n, d]")
+    h = ctypes.c_void_p(None)
+    _check(lib().tsgne_build_P_walks(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, _ptr(X),
+                                     X.shape[1], int(walks), int(length), ctypes.c_uint64(seed), _stream(stream),
+                                     ctypes.byref(h)))
     return Graph(h.value)
 
 
