@@ -385,12 +385,58 @@ def run_sp(args) -> int:
     return 0
 
 
+def run_walks(args) -> int:
+    """Random-walk P (section 2.1) of the 300,000-node, 1,000,000-edge graph:
+    32 walks of 3 steps from every node."""
+    import numpy as np
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    dev = torch.device("cuda:0")
+    gi = synth.make("dcsbm300k")
+    n, walks, length, seed = gi.n, 32, 3, synth.MASTER_SEED + 9
+    rp, col = tsgne.tsgne_csr_from_edges(n, gi.edges)
+    d_rp, d_col, d_X = (torch.from_numpy(a).to(dev) for a in (rp, col, gi.X))
+    for _ in range(max(args.warmup, 1)):
+        tsgne.tsgne_build_P_walks(d_rp, d_col, d_X, walks, length, seed).close()
+    reps = max(args.steps, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = tsgne.tsgne_build_P_walks(d_rp, d_col, d_X, walks, length, seed)
+        support = g.info()[1]
+        g.close()
+    torch.cuda.synchronize()
+    avg_s = (time.perf_counter() - t0) / reps
+    steps = n * walks * length
+    result = {
+        "metric": "random-walk P construction, walk steps/s",
+        "value": steps / avg_s, "unit": "walk-steps/s", "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 1),
+        "ms_per_step": avg_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 transition sums, u64 keys", "data": "synthetic",
+        "config": {"workload": "walks_dcsbm300k", "nodes": n, "stored_entries": int(col.shape[0]), "d": gi.d,
+                   "walks_per_node": walks, "length": length, "support_entries": int(support),
+                   "step": "CSR check + distances + transition sums + walks + sort + support CSR + graph set-up"},
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.walk_P(rp, col, gi.X, walks, length, seed)
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": steps / cpu_s, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
+                                  "sample": "the whole construction, %.2f s" % cpu_s}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse or sp")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp or walks")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
     ap.add_argument("--sparse-nodes", type=int, default=10_000_000, help="sparse: nodes of the SBM")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
@@ -421,6 +467,8 @@ def main() -> int:
         return run_sparse(args)
     if args.workload == "sp":
         return run_sp(args)
+    if args.workload == "walks":
+        return run_walks(args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

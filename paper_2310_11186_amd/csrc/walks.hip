@@ -10,8 +10,9 @@
 // function of its indices.  One thread per walk; the next node is found by
 // binary search in the row's running transition weights, which are summed
 // per row in CSR order in FP64 (distances without contraction, in coordinate
-// order).  The endpoints become 64-bit keys (i, j) and (j, i); a radix sort
-// and a run-length encoding give the canonical symmetric CSR and the counts.
+// order).  The endpoints become 64-bit keys i*n + j and j*n + i; a radix
+// sort over the bits those need and a run-length encoding give the canonical
+// symmetric CSR and the counts.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -23,7 +24,7 @@ namespace tsgne {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint64_t kNoKey = ~0ull;  // a walk that ended where it started
+constexpr int kWavesPerBlock = kBlock / kWave;
 
 __device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -47,7 +48,10 @@ __device__ __forceinline__ double walk_uniform(uint64_t seed, int32_t i, int32_t
   return ((double)c[0] * 2097152.0 + (double)(c[1] >> 11)) * 0x1p-53;  // exact
 }
 
-// D_e = ||x_u - x_v||^2 in FP64, coordinates in order, no contraction.
+// D_e = ||x_u - x_v||^2 in FP64, one thread per entry, the coordinates
+// summed in order without contraction (float4 loads when d is a multiple of
+// 4, several in flight).
+template <bool VEC4>
 __global__ __launch_bounds__(kBlock) void k_walk_dist(const int32_t* __restrict__ row_of,
                                                       const int32_t* __restrict__ col, int64_t nnz,
                                                       const float* __restrict__ X, int32_t d,
@@ -57,32 +61,58 @@ __global__ __launch_bounds__(kBlock) void k_walk_dist(const int32_t* __restrict_
   const float* xu = X + (int64_t)row_of[e] * d;
   const float* xv = X + (int64_t)col[e] * d;
   double acc = 0;
-  for (int32_t k = 0; k < d; ++k) {
+  if constexpr (VEC4) {
+#pragma unroll 8
+    for (int32_t k = 0; k < d; k += 4) {
 #pragma clang fp contract(off)
-    const double t = (double)xu[k] - (double)xv[k];
-    acc = acc + t * t;
+      const float4 p = *reinterpret_cast<const float4*>(xu + k);
+      const float4 q = *reinterpret_cast<const float4*>(xv + k);
+      const double t0 = (double)p.x - (double)q.x, t1 = (double)p.y - (double)q.y;
+      const double t2 = (double)p.z - (double)q.z, t3 = (double)p.w - (double)q.w;
+      acc = acc + t0 * t0;
+      acc = acc + t1 * t1;
+      acc = acc + t2 * t2;
+      acc = acc + t3 * t3;
+    }
+  } else {
+    for (int32_t k = 0; k < d; ++k) {
+#pragma clang fp contract(off)
+      const double t = (double)xu[k] - (double)xv[k];
+      acc = acc + t * t;
+    }
   }
   D[e] = acc;
 }
 
-// Running transition weights of each row, in CSR order:
-// C_e = sum over the row's entries up to e of exp(-(D - D_min)).
-__global__ __launch_bounds__(kBlock) void k_walk_cdf(const int32_t* __restrict__ row_ptr, int32_t n,
-                                                     double* __restrict__ C) {
-  const int32_t u = blockIdx.x * kBlock + threadIdx.x;
-  if (u >= n) return;
+// Running transition weights, one wave per row u, in CSR order:
+// C_e = sum over the row's entries up to e of exp(-(D - D_min)), in place
+// over D.  Lanes take 64 entries at a time; the running sum is carried
+// through the lanes one by one, so it is the sequential sum.
+__global__ __launch_bounds__(kBlock) void k_walk_weights(const int32_t* __restrict__ row_ptr, int32_t n,
+                                                         double* __restrict__ C) {
+  const int32_t u = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (u >= n) return;  // whole wave
+  const int lane = threadIdx.x & (kWave - 1);
   const int32_t a = row_ptr[u], b = row_ptr[u + 1];
   double dmin = INFINITY;
-  for (int32_t e = a; e < b; ++e) dmin = fmin(dmin, C[e]);
-  double run = 0;
-  for (int32_t e = a; e < b; ++e) {
-    run = run + exp(-(C[e] - dmin));
-    C[e] = run;
+  for (int32_t e = a + lane; e < b; e += kWave) dmin = fmin(dmin, C[e]);
+  for (int off = kWave / 2; off > 0; off >>= 1) dmin = fmin(dmin, __shfl_xor(dmin, off, kWave));
+  double run = 0;  // the same in every lane
+  for (int32_t c0 = a; c0 < b; c0 += kWave) {
+    const int32_t e = c0 + lane;
+    const double w = e < b ? exp(-(C[e] - dmin)) : 0.0;
+    const int cnt = min(kWave, b - c0);
+    double mine = 0;
+    for (int j = 0; j < cnt; ++j) {
+      run = run + __shfl(w, j, kWave);
+      if (lane == j) mine = run;
+    }
+    if (e < b) C[e] = mine;
   }
 }
 
-// One thread per walk: its endpoint as the keys (i, j) and (j, i), or two
-// kNoKey when it ends at its start.
+// One thread per walk: its endpoint as the keys i*n + j and j*n + i, or two
+// n*n (after every pair) when it ends at its start.
 __global__ __launch_bounds__(kBlock) void k_walks(const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col, const double* __restrict__ C,
                                                   int32_t n, int32_t walks, int32_t length, uint64_t seed,
@@ -103,29 +133,29 @@ __global__ __launch_bounds__(kBlock) void k_walks(const int32_t* __restrict__ ro
     }
     u = col[lo];
   }
-  uint64_t k0 = kNoKey, k1 = kNoKey;
+  uint64_t k0 = (uint64_t)n * n, k1 = k0;
   if (u != i) {
-    k0 = ((uint64_t)(uint32_t)i << 32) | (uint32_t)u;
-    k1 = ((uint64_t)(uint32_t)u << 32) | (uint32_t)i;
+    k0 = (uint64_t)i * n + u;
+    k1 = (uint64_t)u * n + i;
   }
   keys[2 * t] = k0;
   keys[2 * t + 1] = k1;
 }
 
-// CSR and P from the distinct sorted keys and their counts; total keys of
-// non-returning walks = 2 M.
+// CSR and P from the distinct sorted keys (i*n + j) and their counts; total
+// keys of non-returning walks = 2 M.
 __global__ __launch_bounds__(kBlock) void k_walk_csr(const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ counts, int64_t total, int32_t n,
                                                      double two_m, int32_t* __restrict__ row_ptr,
                                                      int32_t* __restrict__ col, float* __restrict__ P) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t < total) {
-    col[t] = (int32_t)(keys[t] & 0xffffffffu);
+    col[t] = (int32_t)(keys[t] % (uint64_t)n);
     P[t] = (float)((double)counts[t] / two_m);
   }
   if (t <= n) {  // row_ptr[t] = first key with row >= t
     int64_t lo = 0, hi = total;
-    const uint64_t target = (uint64_t)t << 32;
+    const uint64_t target = (uint64_t)t * n;
     while (lo < hi) {
       const int64_t mid = lo + (hi - lo) / 2;
       if (keys[mid] < target) lo = mid + 1;
@@ -159,9 +189,12 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
   const int64_t n_keys = 2 * (int64_t)n * walks;
+  const uint64_t no_key = (uint64_t)n * n;  // a walk that ended where it started
+  int end_bit = 1;
+  while (end_bit < 64 && (no_key >> end_bit) != 0) ++end_bit;  // keys are at most n*n
   size_t sort_bytes = 0, rle_bytes = 0;
   TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                              (int)n_keys, 0, 64, s),
+                                              (int)n_keys, 0, end_bit, s),
             "size sort");
   TSGNE_HIP(hipcub::DeviceRunLengthEncode::Encode(nullptr, rle_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
                                                   (int32_t*)nullptr, (int64_t*)nullptr, (int)n_keys, s),
@@ -210,14 +243,19 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
   void* const cub_tmp = base + o_tmp;
 
   if (nnz > 0) {
-    hipLaunchKernelGGL(k_walk_dist, dim3(blocks_for(nnz)), dim3(kBlock), 0, s, row_of, col_d, nnz, X_d, d, C);
-    hipLaunchKernelGGL(k_walk_cdf, dim3(blocks_for(n)), dim3(kBlock), 0, s, row_ptr_d, n, C);
+    if (d % 4 == 0)
+      hipLaunchKernelGGL(k_walk_dist<true>, dim3(blocks_for(nnz)), dim3(kBlock), 0, s, row_of, col_d, nnz, X_d, d, C);
+    else
+      hipLaunchKernelGGL(k_walk_dist<false>, dim3(blocks_for(nnz)), dim3(kBlock), 0, s, row_of, col_d, nnz, X_d, d, C);
+    hipLaunchKernelGGL(k_walk_weights, dim3((unsigned)(((int64_t)n + kWavesPerBlock - 1) / kWavesPerBlock)),
+                       dim3(kBlock), 0, s, row_ptr_d, n, C);
   }
   hipLaunchKernelGGL(k_walks, dim3(blocks_for((int64_t)n * walks)), dim3(kBlock), 0, s, row_ptr_d, col_d, C, n, walks,
                      length, seed, keys);
   TSGNE_HIP(hipGetLastError(), "launch walks");
   size_t bytes = sort_bytes;
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, bytes, keys, sorted, (int)n_keys, 0, 64, s), "sort endpoints");
+  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, bytes, keys, sorted, (int)n_keys, 0, end_bit, s),
+            "sort endpoints");
   bytes = rle_bytes;
   TSGNE_HIP(hipcub::DeviceRunLengthEncode::Encode(cub_tmp, bytes, sorted, runs, counts, n_runs, (int)n_keys, s),
             "count endpoints");
@@ -231,7 +269,7 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
     TSGNE_HIP(hipMemcpy(&last_count, counts + host_runs - 1, sizeof(int32_t), hipMemcpyDeviceToHost),
               "read last count");
   }
-  const bool has_returns = host_runs > 0 && last_key == kNoKey;
+  const bool has_returns = host_runs > 0 && last_key == no_key;
   const int64_t total = host_runs - (has_returns ? 1 : 0);
   const int64_t two_m = n_keys - (has_returns ? last_count : 0);
   hipLaunchKernelGGL(k_walk_csr, dim3(blocks_for(std::max<int64_t>(total, (int64_t)n + 1))), dim3(kBlock), 0, s, runs,
