@@ -129,7 +129,7 @@ TSGNE_API tsgne_status tsgne_knn_graph(int32_t n, int64_t nnz, const int32_t* ro
  * The ShortestPath graph embedding of section 2.3, eq. (8): X[i][j] is the
  * hop distance between node i and target t_j when it is at most l0, and
  * l0 + 1 when it is larger or t_j cannot be reached from i.  Readings: the
- * condition of eq. (8) is on d_ij, and the equation's "at most l0" is
+ * condition of eq. (8) is on d_ij, and the equation (at most l0) is
  * followed.  The paper picks the d targets at random; the caller passes them.
  * X can be passed to tsgne_build_P as the node embedding.
  *   n, nnz, row_ptr_d, col_d -- G as a canonical symmetric CSR (device), as

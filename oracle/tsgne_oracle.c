@@ -544,7 +544,7 @@ void oracle_run(int32_t n, const int32_t* row_ptr, const int32_t* col, const dou
 
 /*
  * Quantised layout coordinates for the clustering of section 2.5.  Reading:
- * the paper clusters the layout with "kNN clustering" whose k is the number
+ * the paper clusters the layout with kNN clustering whose k is the number
  * of graph clusters, read as k-means (Lloyd).  So that every decision of the
  * clustering is reproducible, it runs on the layout mapped onto a 2^24 x 2^24
  * grid over its bounding box: q = min(floor((y - lo) / (hi - lo) * 2^24),
