@@ -206,6 +206,47 @@ TSGNE_API tsgne_status tsgne_aq(int32_t n, const float* Y_d, const int32_t* labe
                                 double p, double* aq_out, void* stream);
 
 /*
+ * Node renumbering for memory locality.  By the premise of t-SGNE (section
+ * 2.2) nodes close in the graph are close in R^d, so numbering the nodes
+ * along a space-filling curve of the embedding puts most graph neighbours at
+ * nearby ids, and the position gathers of the attraction stay within a small
+ * window of Y.  Optional: results in the new numbering map back to the
+ * caller's with tsgne_permute_rows(..., inverse = 1, ...).
+ *
+ * tsgne_locality_order: perm_d[r] = the node of rank r in the Morton
+ * (Z-order) of the leading m = min(d, 8) coordinates of X, each quantised to
+ * b = 64 / m bits over its own range (q = min(floor((x - lo) / (hi - lo) *
+ * 2^b), 2^b - 1), 0 on a flat axis) and interleaved from the top bit down,
+ * coordinate 0 first; ties in node id order.
+ *   X_d    -- float32[n][d] (device);  perm_d -- int32[n] (device, written)
+ * Synchronising.  Errors: E_INVAL, E_NONFINITE, E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_locality_order(int32_t n, const float* X_d, int32_t d, int32_t* perm_d, void* stream);
+
+/*
+ * tsgne_permute_graph: the graph renumbered by perm (new node r = old node
+ * perm[r]): (r, s) is an edge iff (perm[r], perm[s]) is one.  The input is a
+ * canonical symmetric CSR (as for tsgne_build_P); the output is one too.
+ *   perm_d        -- int32[n] (device), a permutation of [0, n)
+ *   out_row_ptr_d -- int32[n+1] (device, written); out_col_d -- int32[nnz]
+ * Synchronising.  Errors: E_INVAL (sizes, perm not a permutation), E_GRAPH,
+ * E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_permute_graph(int32_t n, int64_t nnz, const int32_t* row_ptr_d, const int32_t* col_d,
+                                           const int32_t* perm_d, int32_t* out_row_ptr_d, int32_t* out_col_d,
+                                           void* stream);
+
+/*
+ * tsgne_permute_rows: rows of row_bytes bytes (a multiple of 4) of a
+ * row-major device array: dst row r = src row perm[r] (inverse = 0, e.g. X
+ * or Y0 into the new numbering), or dst row perm[r] = src row r (inverse =
+ * 1, e.g. a layout back into the old numbering).  src and dst must not
+ * overlap.  Asynchronous on the stream.  Errors: E_INVAL, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_permute_rows(int32_t n, int32_t row_bytes, const void* src_d, const int32_t* perm_d,
+                                          int32_t inverse, void* dst_d, void* stream);
+
+/*
  * Builds the joint affinities P of eq. (3) from the conditional affinities of
  * eq. (2) over each node's graph neighbours (section 2.2), with the bandwidth
  * of each row set by bisection so that its perplexity equals `perplexity`

@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "philox4x32_10", "walk_P", "mirror", "edge_sqdist", "calibrate",
+    "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "philox4x32_10", "walk_P", "locality_order", "mirror", "edge_sqdist", "calibrate",
     "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
@@ -60,6 +60,7 @@ def lib():
             "oracle_shortest_path_embedding": (ctypes.c_int, [i32, vp, vp, i32, vp, dbl, vp]),
             "oracle_kmeans": (ctypes.c_int, [i32, vp, i32, vp, i32, vp, vp]),
             "oracle_philox4x32_10": (None, [vp, vp, vp]),
+            "oracle_locality_order": (ctypes.c_int, [i32, vp, i32, vp]),
             "oracle_walk_P": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp, vp, vp, vp]),
             "oracle_nmi": (dbl, [i32, vp, i32, vp, i32]),
             "oracle_aq": (dbl, [i32, vp, vp, i32, i32, dbl]),
@@ -197,6 +198,17 @@ def walk_P(row_ptr, col, X, walks: int, length: int, seed: int):
     if rc != 0:
         raise OracleError("walk_P failed (%d)" % rc)
     return orp, ocol[: nnz.value].copy(), P[: nnz.value].copy()
+
+
+def locality_order(X) -> np.ndarray:
+    """perm int32[n]: the nodes in Morton order of their leading embedding coordinates."""
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    perm = np.zeros(n, np.int32)
+    rc = lib().oracle_locality_order(n, _p(X), d, _p(perm))
+    if rc != 0:
+        raise OracleError("locality_order failed (%d)" % rc)
+    return perm
 
 
 def mirror(row_ptr, col) -> np.ndarray:

@@ -881,3 +881,79 @@ int oracle_walk_P(int32_t n, const int32_t* row_ptr, const int32_t* col, const f
   free(keys);
   return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Locality order of the nodes by their embedding.                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  uint64_t key;
+  int32_t id;
+} keyed_node;
+
+static int cmp_keyed(const void* a, const void* b) {
+  const keyed_node* x = (const keyed_node*)a;
+  const keyed_node* y = (const keyed_node*)b;
+  if (x->key != y->key) return (x->key > y->key) - (x->key < y->key);
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+/*
+ * A node order along a space-filling curve of the embedding.  The premise of
+ * t-SGNE (section 2.2) is that nodes close in the graph are close in R^d, so
+ * numbering the nodes in this order puts most graph neighbours at nearby
+ * ids.  Definition: m = min(d, 8) leading coordinates, b = 64 / m bits each;
+ * coordinate c of node i is quantised over its own range as
+ * q = min(floor((x - lo) / (hi - lo) * 2^b), 2^b - 1) (0 on a flat axis); the
+ * key is the Morton code that takes bit t of q_0, ..., q_{m-1} (in that
+ * order) for t = b - 1 down to 0, most significant first.  perm[r] is the
+ * node of rank r under (key, node id).
+ */
+int oracle_locality_order(int32_t n, const float* X, int32_t d, int32_t* perm) {
+  if (n < 1 || d < 1) return ORACLE_EINVAL;
+  const int m = d < 8 ? d : 8;
+  const int b = 64 / m;
+  keyed_node* kn = (keyed_node*)calloc((size_t)n, sizeof(keyed_node));
+  uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * m);
+  if (!kn || !q) {
+    free(kn);
+    free(q);
+    return ORACLE_ENOMEM;
+  }
+  const double scale = ldexp(1.0, b);
+  const uint64_t top = (b == 64) ? ~0ull : ((1ull << b) - 1);
+  for (int c = 0; c < m; ++c) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t i = 0; i < n; ++i) {
+      const double v = (double)X[(int64_t)i * d + c];
+      if (!isfinite(v)) {
+        free(kn);
+        free(q);
+        return ORACLE_EINVAL;
+      }
+      if (v < lo) lo = v;
+      if (v > hi) hi = v;
+    }
+    const double span = hi - lo;
+    for (int32_t i = 0; i < n; ++i) {
+      uint64_t u = 0;
+      if (span > 0) {
+        const double t = floor(((double)X[(int64_t)i * d + c] - lo) / span * scale);
+        u = t >= (double)top ? top : (uint64_t)t;
+      }
+      q[(int64_t)i * m + c] = u;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t key = 0;
+    for (int t = b - 1; t >= 0; --t)
+      for (int c = 0; c < m; ++c) key = (key << 1) | ((q[(int64_t)i * m + c] >> t) & 1u);
+    kn[i].key = key;
+    kn[i].id = i;
+  }
+  qsort(kn, (size_t)n, sizeof(keyed_node), cmp_keyed);
+  for (int32_t r = 0; r < n; ++r) perm[r] = kn[r].id;
+  free(kn);
+  free(q);
+  return ORACLE_OK;
+}

@@ -12,7 +12,8 @@
 
 namespace tsgne {
 
-constexpr int kBatchBlockRows = 256;  // rows per update block; attraction blocks cover 1/8 of that
+constexpr int kBatchBlockRows = 256;  // rows per update block
+constexpr int kBatchAttractRows = 256 / kAttractRowLanes;  // rows per attraction block
 
 BatchRun::~BatchRun() {
   if (tables_) (void)hipFree(tables_);
@@ -57,7 +58,7 @@ tsgne_status BatchRun::setup(const BatchMember* m, int32_t count, int32_t R, con
     int64_t li = 0;
     for (int32_t a = 0; a < ws.plan.nb; ++a)
       for (int32_t b = a; b < ws.plan.nb; ++b, ++li) (a == b ? diag_items : items).push_back(make_int4(k, a, b, (int)li));
-    for (int32_t r = 0; r < g->n; r += kBatchBlockRows / 8) chunks.push_back(make_int2(k, r));
+    for (int32_t r = 0; r < g->n; r += kBatchAttractRows) chunks.push_back(make_int2(k, r));
     for (int32_t r = 0; r < g->n; r += kBatchBlockRows) blocks.push_back(make_int2(k, r));
     if (g->n_heavy > 0) {
       std::vector<int32_t> h((size_t)g->n_heavy);

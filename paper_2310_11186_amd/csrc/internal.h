@@ -17,6 +17,9 @@ constexpr int kWave = 64;
 
 // Degree above which a row is handled by a whole wave (calibration, attraction).
 constexpr int32_t kHeavyDegree = 64;
+// Lanes per row in the attraction of rows up to kHeavyDegree entries (the
+// single-graph and batched kernels must agree: it fixes the summation order).
+constexpr int kAttractRowLanes = 8;
 
 // Bits of the device error word written by the CSR check.
 enum : uint32_t {

@@ -350,7 +350,8 @@ __global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ z
 // Attraction sum_j p_ij w_ij (y_i - y_j) over the stored entries of row i
 // (the p-part of the gradient of eq. (5); alpha is applied in the update).
 // Light rows: eight lanes per row.  Heavy rows: one wave per row.
-constexpr int kRowLanes = 8;
+constexpr int kRowLanes = kAttractRowLanes;
+constexpr uint32_t kXcds = 8;  // XCDs of an MI355X (gfx950)
 
 template <int LANES, bool SPLIT>
 __device__ __forceinline__ void attract_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -413,7 +414,12 @@ __global__ __launch_bounds__(kBlock) void k_attract_light(const int32_t* __restr
                                                           const int32_t* __restrict__ col, const float* __restrict__ P,
                                                           const float2* __restrict__ Y, int32_t n,
                                                           double2* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // Blocks are dealt to the XCDs in turn; renumber them so that each XCD
+  // takes one contiguous range of rows, and its L2 sees the neighbours of
+  // nearby rows (the grid is a multiple of kXcds).
+  const uint32_t per_xcd = gridDim.x / kXcds;
+  const uint32_t block = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  const int64_t t = (int64_t)block * kBlock + threadIdx.x;
   const int32_t i = (int32_t)min<int64_t>(t / kRowLanes, n - 1);
   const bool live = t / kRowLanes < n && (row_ptr[i + 1] - row_ptr[i]) <= kHeavyDegree;
   // whole 8-lane groups share `live`, so the shuffles inside stay in step
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(kZThreads) void k_batch_zsum(const BatchDesc* __res
   zsum_block<SPLIT>(d.zpart, d.zpart32, d.n_items, d.Z);
 }
 
-// One block of 256 threads covers 32 light rows of one graph (8 lanes each).
+// One block of 256 threads covers kBlock / kRowLanes light rows of one graph.
 template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_batch_attract_light(const BatchDesc* __restrict__ descs,
                                                                 const int2* __restrict__ chunks) {
@@ -691,10 +697,11 @@ hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s) {
 hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, double2* out, hipStream_t s) {
   const bool split = precision != TSGNE_PREC_FP32;
   const unsigned lb = blocks_for((int64_t)g->n * kRowLanes, kBlock);
+  const unsigned lb8 = (lb + kXcds - 1) / kXcds * kXcds;  // whole rounds over the XCDs
   if (split)
-    hipLaunchKernelGGL(k_attract_light<true>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
+    hipLaunchKernelGGL(k_attract_light<true>, dim3(lb8), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
   else
-    hipLaunchKernelGGL(k_attract_light<false>, dim3(lb), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
+    hipLaunchKernelGGL(k_attract_light<false>, dim3(lb8), dim3(kBlock), 0, s, g->row_ptr, g->col, g->P, Y, g->n, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g->n_heavy == 0) return e;
   const unsigned hb = blocks_for(g->n_heavy, kWavesPerBlock);

@@ -36,7 +36,7 @@ TSGNE_REPULSION_SYMMETRIC = 2
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
-    "tsgne_build_P_walks",
+    "tsgne_build_P_walks", "tsgne_locality_order", "tsgne_permute_graph", "tsgne_permute_rows",
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
@@ -134,6 +134,9 @@ def lib():
             "tsgne_aq": (st, [i32, vp, vp, i32, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]),
             "tsgne_build_P_walks": (st, [i32, i64, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp,
                                          ctypes.POINTER(vp)]),
+            "tsgne_locality_order": (st, [i32, vp, i32, vp, vp]),
+            "tsgne_permute_graph": (st, [i32, i64, vp, vp, vp, vp, vp, vp]),
+            "tsgne_permute_rows": (st, [i32, i32, vp, vp, i32, vp, vp]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -294,6 +297,42 @@ def tsgne_aq(Y, labels, n_labels: int, grid: int, p: float, stream=None) -> floa
     _check(lib().tsgne_aq(Y.shape[0], _ptr(Y), _ptr(labels), int(n_labels), int(grid), float(p), ctypes.byref(out),
                           _stream(stream)))
     return out.value
+
+
+def tsgne_locality_order(X, stream=None):
+    """perm (int32 device tensor): nodes in Morton order of their leading embedding coordinates."""
+    import torch
+    _require(X, torch.float32, name="X")
+    perm = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    _check(lib().tsgne_locality_order(X.shape[0], _ptr(X), X.shape[1], _ptr(perm), _stream(stream)))
+    return perm
+
+
+def tsgne_permute_graph(row_ptr, col, perm, stream=None):
+    """(row_ptr, col) of the graph renumbered by perm (new node r = old node perm[r])."""
+    import torch
+    _require(row_ptr, torch.int32, name="row_ptr")
+    _require(col, torch.int32, name="col")
+    _require(perm, torch.int32, name="perm")
+    n = row_ptr.shape[0] - 1
+    out_rp = torch.empty_like(row_ptr)
+    out_col = torch.empty(max(col.shape[0], 1), dtype=torch.int32, device=col.device)
+    _check(lib().tsgne_permute_graph(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, _ptr(perm),
+                                     _ptr(out_rp), _ptr(out_col), _stream(stream)))
+    return out_rp, out_col[: col.shape[0]]
+
+
+def tsgne_permute_rows(src, perm, inverse: bool = False, stream=None):
+    """Row r of the result = src row perm[r] (or, inverse, result row perm[r] = src row r)."""
+    import torch
+    _require(perm, torch.int32, name="perm")
+    if not src.is_cuda or not src.is_contiguous():
+        raise TypeError("src must be a contiguous device tensor")
+    dst = torch.empty_like(src)
+    row_bytes = src[0].numel() * src.element_size() if src.dim() > 1 else src.element_size()
+    _check(lib().tsgne_permute_rows(src.shape[0], row_bytes, _ptr(src), _ptr(perm), 1 if inverse else 0, _ptr(dst),
+                                    _stream(stream)))
+    return dst
 
 
 class Graph:

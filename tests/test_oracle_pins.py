@@ -627,3 +627,37 @@ def test_walk_P_invariants():
     assert np.array_equal(again[1], ocol) and np.array_equal(again[2], P)
     other = oracle.walk_P(rp, col, gi.X, 20, 4, 100)
     assert not (len(other[1]) == len(ocol) and np.array_equal(other[1], ocol) and np.array_equal(other[2], P))
+
+
+# ---------------------------------------------------------------------------
+# Locality order: Morton order of the leading embedding coordinates
+# ---------------------------------------------------------------------------
+
+def test_locality_order_one_coordinate_is_sorting():
+    x = np.random.default_rng(0).standard_normal((1000, 1)).astype(np.float32)
+    x[10] = x[20]                                   # a tie: lower id first
+    assert np.array_equal(oracle.locality_order(x), np.argsort(x[:, 0], kind="stable"))
+
+
+def test_locality_order_z_curve():
+    # a 4 x 4 grid: the Z curve visits quadrants (coordinate 0 first), then
+    # the points inside each quadrant in the same pattern
+    pts = np.array([[a, b] for a in range(4) for b in range(4)], np.float32)
+    order = [tuple(int(v) for v in pts[i]) for i in oracle.locality_order(pts)]
+    assert order == [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (0, 3), (1, 2), (1, 3),
+                     (2, 0), (2, 1), (3, 0), (3, 1), (2, 2), (2, 3), (3, 2), (3, 3)]
+    corners = np.array([[0, 0], [1, 1], [0, 1], [1, 0]], np.float32)
+    assert oracle.locality_order(corners).tolist() == [0, 2, 3, 1]
+
+
+def test_locality_order_brings_graph_neighbours_together():
+    gi = synth.small_sbm(20000, 40, 8.0, 8, 3)
+    perm = oracle.locality_order(gi.X)
+    assert np.array_equal(np.sort(perm), np.arange(gi.n))
+    rank = np.empty(gi.n, np.int64)
+    rank[perm] = np.arange(gi.n)
+    gap = np.abs(rank[gi.edges[:, 0]] - rank[gi.edges[:, 1]])
+    intra = gi.labels[gi.edges[:, 0]] == gi.labels[gi.edges[:, 1]]
+    assert np.median(gap[intra]) < gi.n / 40           # random numbering: about n / 3
+    x = np.random.default_rng(1).standard_normal((50, 12)).astype(np.float32)
+    assert np.array_equal(np.sort(oracle.locality_order(x)), np.arange(50))    # d > 8: leading 8 used
