@@ -238,6 +238,8 @@ def run_serve(args) -> int:
     log("served at %.2f req/s: p50 %.0f ms, p99 %.0f ms" % (qps, st["latency_p50_ms"], st["latency_p99_ms"]))
     st1, wall1 = serve_stream(kw1, reqs, arrivals, n_iter)
     log("one at a time: p50 %.0f ms, p99 %.0f ms" % (st1["latency_p50_ms"], st1["latency_p99_ms"]))
+    st_eq, wall_eq = serve_stream(dict(kw, oldest_share=0.0), reqs, arrivals, n_iter)
+    log("equal shares: p50 %.0f ms, p99 %.0f ms" % (st_eq["latency_p50_ms"], st_eq["latency_p99_ms"]))
     pairs = sum(float(gi.n) * (gi.n - 1) for gi in reqs) * n_iter
     result = {
         "metric": "served layouts/s with p50/p99 latency (Poisson arrivals, continuous batching)",
@@ -247,7 +249,8 @@ def run_serve(args) -> int:
         "config": {"workload": "serve", "requests": count, "n_iter": n_iter, "qps": qps,
                    "nodes_range": [1000, 200000], "nodes_total": int(sum(gi.n for gi in reqs)),
                    "tile_rows": kw["tile_rows"], "steps_per_round": kw["steps_per_round"],
-                   "round_ms": kw["round_ms"], "max_active": kw["max_active"]},
+                   "round_ms": kw["round_ms"], "max_active": kw["max_active"],
+                   "oldest_share": "library default (0.5)"},
         "latency_p50_ms": st["latency_p50_ms"], "latency_p99_ms": st["latency_p99_ms"],
         "pair_interactions_per_s": pairs / wall,
         "saturated": {"layouts_per_s": sat_rate, "seconds": wall_sat,
@@ -255,6 +258,8 @@ def run_serve(args) -> int:
                       "speedup_vs_one_at_a_time": wall_sat1 / wall_sat},
         "one_at_a_time": {"layouts_per_s": count / wall1, "latency_p50_ms": st1["latency_p50_ms"],
                           "latency_p99_ms": st1["latency_p99_ms"], "seconds": wall1},
+        "equal_shares": {"layouts_per_s": count / wall_eq, "latency_p50_ms": st_eq["latency_p50_ms"],
+                         "latency_p99_ms": st_eq["latency_p99_ms"], "seconds": wall_eq},
     }
     print(json.dumps(result), flush=True)
     return 0

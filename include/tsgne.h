@@ -430,6 +430,9 @@ typedef struct tsgne_server_config {
   int32_t tile_rows;       /* repulsion tile of every request: 4, 8 (default), 12, 14, 15 or 16 */
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
   float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
+  float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared
+                              equally (default 0.5; 0 = equal shares for all); bounds how far small arrivals can
+                              slow the request that has waited longest */
 } tsgne_server_config;
 
 typedef struct tsgne_request {

@@ -279,13 +279,22 @@ void tsgne_server::run() {
     // Steps per request this round: an equal share of the round's target time
     // (small graphs take many steps, large ones few), or the same count for
     // all when no target is set.
+    // With oldest_share > 0 the request that has waited longest gets that
+    // fraction of the round and the others split the rest.
     std::vector<int32_t> take(active.size()), lim(active.size());
     int32_t longest = 1;
     double pairs = 0.0;
-    const double share = cfg.round_ms > 0.f ? pair_rate * 1e-3 * cfg.round_ms / (double)active.size() : 0.0;
+    const double budget = cfg.round_ms > 0.f ? pair_rate * 1e-3 * cfg.round_ms : 0.0;
+    size_t oldest = 0;
+    for (size_t k = 1; k < active.size(); ++k)
+      if (active[k].req->t_submit < active[oldest].req->t_submit) oldest = k;
+    const bool favour = cfg.oldest_share > 0.f && active.size() > 1;
     for (size_t k = 0; k < active.size(); ++k) {
       const Slot& sl = active[k];
       const double per_step = (double)sl.req->n * (double)(sl.req->n - 1) + 1.0;
+      const double share = !favour ? budget / (double)active.size()
+                           : k == oldest ? budget * cfg.oldest_share
+                                         : budget * (1.0 - cfg.oldest_share) / (double)(active.size() - 1);
       int32_t steps = cfg.steps_per_round;
       if (share > 0.0) steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
       steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
@@ -384,6 +393,7 @@ void tsgne_server_config_default(tsgne_server_config* c) {
   c->max_queue = 1 << 20;
   c->steps_per_round = 64;
   c->round_ms = 25.0f;
+  c->oldest_share = 0.5f;
   c->tile_rows = 8;
   tsgne_params_default(&c->params);
 }
@@ -393,6 +403,8 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
   *out = nullptr;
   if (tsgne_status st = validate_params(&cfg->params)) return st;
   if (!std::isfinite(cfg->round_ms)) return fail(TSGNE_E_INVAL, "round_ms must be finite");
+  if (!(cfg->oldest_share >= 0.f && cfg->oldest_share < 1.f))
+    return fail(TSGNE_E_INVAL, "oldest_share must lie in [0, 1)");
   if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
     return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
   if (!tile_rows_supported(cfg->tile_rows)) return fail(TSGNE_E_INVAL, "tile_rows must be 4, 8, 12, 14, 15 or 16");

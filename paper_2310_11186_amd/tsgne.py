@@ -81,6 +81,7 @@ class tsgne_server_config(ctypes.Structure):
         ("tile_rows", ctypes.c_int32),
         ("params", tsgne_params),
         ("round_ms", ctypes.c_float),
+        ("oldest_share", ctypes.c_float),
     ]
 
 
@@ -510,7 +511,7 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
                  steps_per_round: int = 64, tile_rows: int = 8, params: tsgne_params | None = None,
-                 round_ms: float = 25.0):
+                 round_ms: float = 25.0, oldest_share: float | None = None):
         cfg = tsgne_server_config()
         lib().tsgne_server_config_default(ctypes.byref(cfg))
         cfg.hbm_budget = int(hbm_budget)
@@ -519,6 +520,8 @@ class Server:
         cfg.steps_per_round = int(steps_per_round)
         cfg.tile_rows = int(tile_rows)
         cfg.round_ms = float(round_ms)
+        if oldest_share is not None:
+            cfg.oldest_share = float(oldest_share)
         if params is not None:
             cfg.params = params
         h = ctypes.c_void_p(None)

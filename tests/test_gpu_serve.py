@@ -32,9 +32,10 @@ def requests(seed):
     return gis, iters
 
 
-@pytest.mark.parametrize("max_active,budget_scale,round_ms", [(3, 0, 25.0), (64, 1.3, 25.0), (64, 0, 0.0),
-                                                            (64, 0, 0.05)])
-def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms):
+@pytest.mark.parametrize("max_active,budget_scale,round_ms,oldest", [(3, 0, 25.0, 0.5), (64, 1.3, 25.0, 0.5),
+                                                                     (64, 0, 0.0, 0.5), (64, 0, 0.05, 0.5),
+                                                                     (64, 0, 0.05, 0.0), (64, 0, 0.05, 0.9)])
+def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
     gis, iters = requests(1)
     budget = 0
     if budget_scale:
@@ -43,7 +44,7 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms):
         nb = (2100 + 64 * R - 1) // (64 * R)
         budget = int(budget_scale * (8 * nb * nb * 64 * R + 2100 * 400 + 40 * 2100 * 6))
     srv = tsgne.Server(hbm_budget=budget, max_active=max_active, steps_per_round=7, tile_rows=4,
-                       params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms)
+                       params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms, oldest_share=oldest)
     tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
     outs = [srv.wait(t) for t in tickets]
     st = srv.stats()
@@ -76,6 +77,13 @@ def test_failures_stay_with_their_request(gpu):
     st = srv.stats()
     assert st["failed"] == 1 and st["cancelled"] == 1 and st["completed"] == 3
     srv.close()
+
+
+def test_server_config_rejects(gpu):
+    for bad in (1.0, -0.1, float("nan")):
+        with pytest.raises(tsgne.TsgneError) as e:
+            tsgne.Server(oldest_share=bad)
+        assert e.value.status == tsgne.TSGNE_E_INVAL
 
 
 def test_oversize_and_full_queue(gpu):
