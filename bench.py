@@ -57,49 +57,18 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
-def snowball(n: int, edges, size: int, seed: int):
-    """Node set of a BFS from seeded roots until `size` nodes (a sample of the
-    graph that keeps its local density)."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    from collections import deque
-    adj = [[] for _ in range(n)]
-    for u, v in edges:
-        adj[u].append(v)
-        adj[v].append(u)
-    seen = np.zeros(n, bool)
-    order = []
-    while len(order) < size:
-        root = int(rng.integers(0, n))
-        if seen[root]:
-            continue
-        seen[root] = True
-        q = deque([root])
-        while q and len(order) < size:
-            u = q.popleft()
-            order.append(u)
-            for v in adj[u]:
-                if not seen[v]:
-                    seen[v] = True
-                    q.append(v)
-    return np.array(sorted(order[:size]), np.int64)
-
-
 def cpu_baseline(gi, n_iter_total: int, exaggeration_iters: int, perplexity: float, budget_s: float):
     """FP64 oracle on the host: optimisation steps on a 20,000-node snowball
     sample of the same graph, timed until ~budget_s seconds have passed."""
     import numpy as np
 
     import oracle
-    size = min(20_000, gi.n)
-    nodes = snowball(gi.n, gi.edges, size, seed=1)
-    remap = -np.ones(gi.n, np.int64)
-    remap[nodes] = np.arange(size)
-    e = remap[gi.edges.astype(np.int64)]
-    e = e[(e[:, 0] >= 0) & (e[:, 1] >= 0)]
+    from paper_2310_11186_amd import synth
+    sub = synth.snowball_sample(gi, 20_000, seed=1)
+    size, e = sub.n, sub.edges
     rp, col = oracle.csr_from_edges(size, e)
-    P, _ = oracle.build_P(rp, col, gi.X[nodes], perplexity)
-    Y = gi.Y0[nodes].astype(np.float64)
+    P, _ = oracle.build_P(rp, col, sub.X, perplexity)
+    Y = sub.Y0.astype(np.float64)
     U = np.zeros_like(Y)
     G = np.ones_like(Y)
     steps = 0

@@ -273,3 +273,39 @@ def small_dcsbm(n: int, m: int, gamma: float, n_comm: int, d: int, seed: int) ->
     edges, labels = dcsbm(n, m, gamma, n_comm, 0.18, seed)
     X = embedding(labels, d, 0.5, seed)
     return GraphInput(n, edges, labels, X, initial_layout(n, seed), "dcsbm%d" % n)
+
+
+def snowball_sample(gi: GraphInput, size: int, seed: int) -> GraphInput:
+    """The subgraph induced by the nodes a BFS from seeded random roots reaches
+    first (until `size` nodes): a sample that keeps the graph's local density.
+    Nodes keep their relative order; X, labels and Y0 are the sampled rows."""
+    from collections import deque
+    rng = np.random.default_rng(seed)
+    n = gi.n
+    size = min(size, n)
+    adj = [[] for _ in range(n)]
+    for u, v in gi.edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    seen = np.zeros(n, bool)
+    order = []
+    while len(order) < size:
+        root = int(rng.integers(0, n))
+        if seen[root]:
+            continue
+        seen[root] = True
+        q = deque([root])
+        while q and len(order) < size:
+            u = q.popleft()
+            order.append(u)
+            for v in adj[u]:
+                if not seen[v]:
+                    seen[v] = True
+                    q.append(v)
+    nodes = np.array(sorted(order[:size]), np.int64)
+    remap = -np.ones(n, np.int64)
+    remap[nodes] = np.arange(size)
+    e = remap[gi.edges.astype(np.int64)]
+    e = e[(e[:, 0] >= 0) & (e[:, 1] >= 0)].astype(np.int32)
+    return GraphInput(size, e, gi.labels[nodes], np.ascontiguousarray(gi.X[nodes]), np.ascontiguousarray(gi.Y0[nodes]),
+                      "%s_snowball%d" % (gi.name, size))

@@ -81,3 +81,47 @@ def test_precision_split_vs_fp32(gpu):
         assert sp["traj30_rel_l2"] <= 3 * sp["traj30_fp32_state_oracle_drift"] + 1e-4
         assert sp["kl_abs"] <= 1e-6
     print(json.dumps(report, indent=1))
+
+
+def test_precision_c3_subsample(gpu):
+    """The 300K-node graph's precision check on a 20,000-node BFS snowball
+    sample: 250 steps in the split mode and in all-FP32 against the FP64
+    oracle (KL of the final layouts; gradient and Z at the oracle's final
+    state, where the comparison is free of trajectory chaos)."""
+    import torch
+    sub = synth.snowball_sample(synth.make("dcsbm300k"), 20_000, seed=1)
+    steps, t_ee = 250, 62
+    rp, col = tsgne.tsgne_csr_from_edges(sub.n, sub.edges)
+    g = tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                            torch.from_numpy(sub.X).to(gpu), 30.0)
+    oP, _ = oracle.build_P(rp, col, sub.X, 30.0)
+    eta = max(sub.n / 48.0, 50.0)
+    oY, _, _, _ = oracle.run(rp, col, oP, sub.Y0, n_steps=steps, exaggeration_iters=t_ee, eta=eta)
+    o_kl = oracle.kl(rp, col, oP, oY)
+    og, oZ = oracle.gradient(rp, col, oP, oY, 1.0)
+    entry = {"nodes": sub.n, "edges": int(sub.edges.shape[0]), "steps": steps, "oracle_kl": o_kl,
+             "P_rel_l2": rel_l2(g.export()["P"], oP)}
+    for name, mode in (("split", tsgne.TSGNE_PREC_SPLIT), ("fp32", tsgne.TSGNE_PREC_FP32)):
+        p = tsgne.tsgne_params_default(precision=mode, exaggeration_iters=t_ee, learning_rate=eta)
+        Yg = torch.from_numpy(sub.Y0).to(gpu)
+        tsgne.tsgne_run(g, Yg, steps, p)
+        kl = tsgne.tsgne_kl(g, Yg)
+        grad, Z = tsgne.tsgne_gradient(g, torch.from_numpy(oY.astype(np.float32)).to(gpu), 1.0, p)
+        og32, _ = oracle.gradient(rp, col, oP, f32(oY), 1.0)      # the oracle at the same FP32-rounded state
+        entry[name] = {"kl": kl, "kl_rel_to_oracle": kl / o_kl - 1.0,
+                       "grad_rel_l2_at_oracle_state": rel_l2(grad.cpu().numpy(), og32),
+                       "Z_rel_at_oracle_state": abs(Z.item() / oZ - 1.0),
+                       "traj_rel_l2": rel_l2(Yg.cpu().numpy(), oY)}
+    g.close()
+    if os.path.isdir(OUT):
+        path = os.path.join(OUT, "precision_report.json")
+        report = json.load(open(path)) if os.path.exists(path) else {}
+        report["dcsbm300k_snowball20k"] = entry
+        with open(path, "w") as fh:
+            json.dump(report, fh, indent=1)
+    print(json.dumps(entry, indent=1))
+    sp, fp = entry["split"], entry["fp32"]
+    assert entry["P_rel_l2"] <= 1e-6
+    assert sp["grad_rel_l2_at_oracle_state"] <= 1e-5 and sp["Z_rel_at_oracle_state"] <= 1e-5
+    assert abs(sp["kl_rel_to_oracle"]) <= 0.02
+    assert fp["grad_rel_l2_at_oracle_state"] <= 1e-3 and abs(fp["kl_rel_to_oracle"]) <= 0.05
