@@ -376,6 +376,51 @@ def run_sp(args) -> int:
     return 0
 
 
+def run_knn(args) -> int:
+    """The t-SGNE neighbourhood graph G_knn,G (section 2.2, eq. (7)) of the
+    300,000-node, 1,000,000-edge graph with k = 90 (three times the default
+    perplexity of 30, so that calibration has more neighbours than the
+    perplexity on every row that has them)."""
+    import numpy as np
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    dev = torch.device("cuda:0")
+    gi = synth.make("dcsbm300k")
+    n, k = gi.n, 90
+    rp, col = tsgne.tsgne_csr_from_edges(n, gi.edges)
+    d_rp, d_col = torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev)
+    for _ in range(max(args.warmup, 1)):
+        krp, kcol = tsgne.tsgne_knn_graph(d_rp, d_col, k)
+    reps = max(args.steps, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        krp, kcol = tsgne.tsgne_knn_graph(d_rp, d_col, k)
+    torch.cuda.synchronize()
+    avg_s = (time.perf_counter() - t0) / reps
+    result = {
+        "metric": "G_knn,G construction, source nodes/s",
+        "value": n / avg_s, "unit": "nodes/s", "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 1),
+        "ms_per_step": avg_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "knn_dcsbm300k", "nodes": n, "stored_entries": int(col.shape[0]), "k": k,
+                   "knn_entries": int(kcol.shape[0]),
+                   "step": "CSR check + per-source BFS to k nodes + symmetrisation (sort, unique) + CSR"},
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.knn_graph(rp, col, k)
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": n / cpu_s, "unit": "nodes/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle", "sample": "the whole construction, %.2f s" % cpu_s}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def run_walks(args) -> int:
     """Random-walk P (section 2.1) of the 300,000-node, 1,000,000-edge graph:
     32 walks of 3 steps from every node."""
@@ -427,7 +472,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp or walks")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp, walks or knn")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
     ap.add_argument("--sparse-nodes", type=int, default=10_000_000, help="sparse: nodes of the SBM")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
@@ -460,6 +505,8 @@ def main() -> int:
         return run_sp(args)
     if args.workload == "walks":
         return run_walks(args)
+    if args.workload == "knn":
+        return run_knn(args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
