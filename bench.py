@@ -192,7 +192,7 @@ def run_serve(args) -> int:
     log("generating %d requests" % count)
     reqs = synth.serving_requests(count)
     params = tsgne.tsgne_params_default(exaggeration_iters=n_iter // 4)
-    kw = dict(max_active=64, steps_per_round=64, round_ms=25.0, tile_rows=args.tile_rows or 8, params=params)
+    kw = dict(max_active=64, steps_per_round=64, round_ms=25.0, tile_rows=args.tile_rows, params=params)
     kw1 = dict(kw, max_active=1)
     # saturated rate: everything submitted at once
     st_sat, wall_sat = serve_stream(kw, reqs, [0.0] * count, n_iter)
@@ -209,6 +209,13 @@ def run_serve(args) -> int:
     log("one at a time: p50 %.0f ms, p99 %.0f ms" % (st1["latency_p50_ms"], st1["latency_p99_ms"]))
     st_eq, wall_eq = serve_stream(dict(kw, oldest_share=0.0), reqs, arrivals, n_iter)
     log("equal shares: p50 %.0f ms, p99 %.0f ms" % (st_eq["latency_p50_ms"], st_eq["latency_p99_ms"]))
+    sweep = []
+    for share in [float(v) for v in args.oldest_shares.split(",") if v]:
+        st_s, wall_s = serve_stream(dict(kw, oldest_share=share), reqs, arrivals, n_iter)
+        log("oldest share %.2f: p50 %.0f ms, p99 %.0f ms" % (share, st_s["latency_p50_ms"], st_s["latency_p99_ms"]))
+        sweep.append({"oldest_share": share, "latency_p50_ms": st_s["latency_p50_ms"],
+                      "latency_p99_ms": st_s["latency_p99_ms"], "latency_mean_ms": st_s["latency_mean_ms"],
+                      "seconds": wall_s})
     pairs = sum(float(gi.n) * (gi.n - 1) for gi in reqs) * n_iter
     result = {
         "metric": "served layouts/s with p50/p99 latency (Poisson arrivals, continuous batching)",
@@ -230,6 +237,8 @@ def run_serve(args) -> int:
         "equal_shares": {"layouts_per_s": count / wall_eq, "latency_p50_ms": st_eq["latency_p50_ms"],
                          "latency_p99_ms": st_eq["latency_p99_ms"], "seconds": wall_eq},
     }
+    if sweep:
+        result["oldest_share_sweep"] = sweep
     print(json.dumps(result), flush=True)
     return 0
 
@@ -474,6 +483,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp, walks or knn")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
+    ap.add_argument("--oldest-shares", default="", metavar="LIST",
+                    help="serve: extra runs of the same arrivals with these oldest_share values (comma list)")
     ap.add_argument("--sparse-nodes", type=int, default=10_000_000, help="sparse: nodes of the SBM")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
     ap.add_argument("--repulsion", default="auto", choices=["auto", "direct", "symmetric"])

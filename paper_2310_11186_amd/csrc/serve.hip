@@ -5,9 +5,12 @@
 // device footprint fits the budget (building their affinities), then advances
 // every active request by `steps_per_round` steps in one captured batched
 // sequence (each request at its own step index), and completes the requests
-// that reached n_iter (layout copied out, memory released).  Every request's
-// arithmetic and reduction order depend only on itself and the server's tile
-// size, so its layout is the same alone or in any mix.
+// that reached n_iter (layout copied out, memory released).  Requests are
+// grouped by tile size, one batched plan per group, the groups running on
+// parallel branches of each captured round.  Every request's arithmetic and
+// reduction order depend only on itself and its tile size (a function of its
+// size, or the server's fixed choice), so its layout is the same alone or in
+// any mix.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -33,6 +36,7 @@ double seconds_since(Clock::time_point t0, Clock::time_point t) {
 struct Request {
   uint64_t ticket = 0;
   int32_t n = 0, d = 0, n_iter = 0;
+  int32_t R = 8;  // repulsion tile rows of this request
   float perplexity = 30.f;
   std::vector<int32_t> edges;
   std::vector<float> X, Y0, Y;
@@ -50,6 +54,16 @@ struct Slot {
   int32_t* t = nullptr;
   int32_t progress = 0;    // steps already run (host view)
 };
+
+// Tile rows of a request when the server does not fix them: graphs with
+// enough tiles to fill the GPU by themselves (kLargeRequest nodes: 128 blocks
+// of 1024) take the single-graph plan's choice, the most efficient per pair;
+// smaller ones take 8, whose short tiles keep their steps short in a shared
+// round.
+constexpr int32_t kLargeRequest = 131072;
+int32_t request_tile_rows(int32_t n) {
+  return n >= kLargeRequest ? make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R : 8;
+}
 
 // Device bytes a request holds while active (graph, workspace, state) plus the
 // transient build buffers, for tile rows R.
@@ -208,7 +222,7 @@ void tsgne_server::admit(hipStream_t s) {
     }
     Slot sl;
     sl.req = r;
-    tsgne_status st = build_slot(*r, cfg.tile_rows, s, sl);
+    tsgne_status st = build_slot(*r, r->R, s, sl);
     if (st != TSGNE_OK) {
       finish(sl, st, tsgne_last_error(), false, s);
       continue;
@@ -223,8 +237,18 @@ void tsgne_server::run() {
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
   int32_t* limits = nullptr;  // per-member pause step of the current round
   if (dalloc(&limits, (size_t)cfg.max_active) != hipSuccess) limits = nullptr;
-  BatchRun br;
+  // Requests are grouped by tile size, one batched plan per group.  With
+  // several groups a round forks one branch per group (its own stream) from
+  // the main stream and joins them at the end, so the groups run together.
+  std::map<int32_t, BatchRun> groups;
   bool plan_valid = false;
+  constexpr int kMaxGroups = 6;  // the supported tile sizes
+  hipStream_t branch[kMaxGroups] = {};
+  hipEvent_t fork = nullptr, join[kMaxGroups] = {};
+  bool branches_ok = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; k < kMaxGroups && branches_ok; ++k)
+    branches_ok = hipStreamCreateWithFlags(&branch[k], hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&join[k], hipEventDisableTiming) == hipSuccess;
   std::map<int32_t, hipGraphExec_t> execs;  // captured rounds by length, for the current membership
   auto drop_execs = [&]() {
     for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
@@ -266,14 +290,19 @@ void tsgne_server::run() {
     const Clock::time_point t0 = Clock::now();
     tsgne_status st = limits ? TSGNE_OK : fail(TSGNE_E_NOMEM, "allocate round limits");
     if (st == TSGNE_OK && !plan_valid) {
-      std::vector<BatchMember> m;
+      std::map<int32_t, std::vector<BatchMember>> members;
       for (size_t k = 0; k < active.size(); ++k) {
         Slot& sl = active[k];
         const size_t len = 2 * (size_t)sl.req->n;
-        m.push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t, limits + k,
-                                sl.req->n_iter});
+        members[sl.req->R].push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t,
+                                                 limits + k, sl.req->n_iter});
       }
-      st = br.setup(m.data(), (int32_t)m.size(), cfg.tile_rows, &cfg.params);
+      groups.clear();
+      if (members.size() > 1 && !branches_ok) st = fail(TSGNE_E_DEVICE, "create round branches");
+      for (auto& kv : members) {
+        if (st != TSGNE_OK) break;
+        st = groups[kv.first].setup(kv.second.data(), (int32_t)kv.second.size(), kv.first, &cfg.params);
+      }
       if (st == TSGNE_OK) plan_valid = true;
     }
     // Steps per request this round: an equal share of the round's target time
@@ -315,8 +344,21 @@ void tsgne_server::run() {
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       hipError_t le = hipSuccess;
-      for (int32_t k = 0; e == hipSuccess && k < len && le == hipSuccess; ++k)
-        le = launch_batch_step(br.plan(), cfg.params, s);
+      if (groups.size() == 1) {
+        const BatchRun& br = groups.begin()->second;
+        for (int32_t k = 0; e == hipSuccess && k < len && le == hipSuccess; ++k)
+          le = launch_batch_step(br.plan(), cfg.params, s);
+      } else if (e == hipSuccess) {
+        le = hipEventRecord(fork, s);
+        int gi = 0;
+        for (auto it = groups.begin(); it != groups.end() && le == hipSuccess; ++it, ++gi) {
+          le = hipStreamWaitEvent(branch[gi], fork, 0);
+          for (int32_t k = 0; k < len && le == hipSuccess; ++k)
+            le = launch_batch_step(it->second.plan(), cfg.params, branch[gi]);
+          if (le == hipSuccess) le = hipEventRecord(join[gi], branch[gi]);
+        }
+        for (int k = 0; k < gi && le == hipSuccess; ++k) le = hipStreamWaitEvent(s, join[k], 0);
+      }
       if (e == hipSuccess) e = hipStreamEndCapture(s, &graph);
       if (e == hipSuccess) e = le;
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -380,7 +422,13 @@ void tsgne_server::run() {
     n_active = 0;
     cv_done.notify_all();
   }
+  groups.clear();
   dfree(limits);
+  for (int k = 0; k < kMaxGroups; ++k) {
+    if (branch[k]) (void)hipStreamDestroy(branch[k]);
+    if (join[k]) (void)hipEventDestroy(join[k]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
   if (s) (void)hipStreamDestroy(s);
 }
 
@@ -394,7 +442,7 @@ void tsgne_server_config_default(tsgne_server_config* c) {
   c->steps_per_round = 64;
   c->round_ms = 25.0f;
   c->oldest_share = 0.5f;
-  c->tile_rows = 8;
+  c->tile_rows = 0;
   tsgne_params_default(&c->params);
 }
 
@@ -407,7 +455,8 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
     return fail(TSGNE_E_INVAL, "oldest_share must lie in [0, 1)");
   if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
     return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
-  if (!tile_rows_supported(cfg->tile_rows)) return fail(TSGNE_E_INVAL, "tile_rows must be 4, 8, 12, 14, 15 or 16");
+  if (cfg->tile_rows != 0 && !tile_rows_supported(cfg->tile_rows))
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0 (per request), 4, 8, 12, 14, 15 or 16");
   if (cfg->hbm_budget < 0) return fail(TSGNE_E_INVAL, "hbm_budget must be >= 0");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TSGNE_E_DEVICE, "no HIP device");
@@ -438,7 +487,8 @@ tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uin
   r->d = rq->d;
   r->n_iter = rq->n_iter;
   r->perplexity = rq->perplexity;
-  r->footprint = footprint_bytes(rq->n, rq->m, rq->d, srv->cfg.tile_rows);
+  r->R = srv->cfg.tile_rows ? srv->cfg.tile_rows : request_tile_rows(rq->n);
+  r->footprint = footprint_bytes(rq->n, rq->m, rq->d, r->R);
   if (r->footprint > (size_t)srv->cfg.hbm_budget)
     return fail(TSGNE_E_NOMEM, "request needs more device memory than the server's budget");
   r->edges.assign(rq->edges_h, rq->edges_h + 2 * rq->m);

@@ -510,7 +510,7 @@ class Server:
     numpy arrays; the server copies them in at submission."""
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
-                 steps_per_round: int = 64, tile_rows: int = 8, params: tsgne_params | None = None,
+                 steps_per_round: int = 64, tile_rows: int = 0, params: tsgne_params | None = None,
                  round_ms: float = 25.0, oldest_share: float | None = None):
         cfg = tsgne_server_config()
         lib().tsgne_server_config_default(ctypes.byref(cfg))

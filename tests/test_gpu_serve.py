@@ -56,6 +56,25 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
         assert np.array_equal(Y, alone(gi, k, 4, gpu)), gi.n
 
 
+def test_per_request_tiles_mix_equals_alone(gpu):
+    # tile_rows = 0: small requests take 8 rows, a 140000-node request the
+    # plan's 15 and a 150000-node one 16, so a round runs three batched plans
+    # on parallel branches; each layout still equals its own run alone.
+    gis = [synth.small_sbm(n, 3, 5.0, 8, 300 + k) for k, n in enumerate([900, 2100, 400])]
+    gis += [synth.small_sbm(n, 6, 6.0, 8, 310 + k) for k, n in enumerate([140_000, 150_000])]
+    iters = [40, 25, 60, 12, 9]
+    srv = tsgne.Server(max_active=64, steps_per_round=7, tile_rows=0, round_ms=0.05,
+                       params=tsgne.tsgne_params_default(**PARAMS))
+    tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(gis) and st["failed"] == 0
+    for gi, k, (status, Y) in zip(gis, iters, outs):
+        assert status == tsgne.TSGNE_OK
+        assert np.array_equal(Y, alone(gi, k, 8 if gi.n < 131072 else 0, gpu)), gi.n
+
+
 def test_failures_stay_with_their_request(gpu):
     gis, iters = requests(2)
     bad = synth.small_sbm(500, 2, 4.0, 8, 77)
