@@ -385,6 +385,99 @@ def run_sp(args) -> int:
     return 0
 
 
+def run_shard(args) -> int:
+    """One GPU's share of the repulsion of a 300,000-node layout split over
+    --shards GPUs (the graph size of the default workload): each shard's call
+    (tile kernel, Z reduction, per-row FP64 sums) timed in turn on this GPU.
+    The value is shard 0's rate; every shard's tile-kernel time is reported to
+    show the balance."""
+    import numpy as np
+    import torch
+
+    from paper_2310_11186_amd import synth, tsgne
+
+    dev = torch.device("cuda:0")
+    n, G = 300_000, args.shards
+    Y = torch.from_numpy(synth.initial_layout(n, synth.MASTER_SEED + 9, std=10.0)).to(dev)
+    F = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    Z = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    reps = max(args.steps, 10)
+    per_shard = []
+    avg0 = None
+    for s in range(G):
+        sh = tsgne.Shard(n, s, G, args.tile_rows)
+        R, tiles, pairs = sh.info()
+        # enough warm-up calls for the clocks to settle before the first shard is timed
+        for _ in range(max(args.warmup, 10)):
+            sh.repulsion(Y, F=F, Z=Z, stream=stream)
+        sh.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sh.repulsion(Y, F=F, Z=Z, stream=stream)
+        torch.cuda.synchronize()
+        call_s = (time.perf_counter() - t0) / reps
+        ms, launches = sh.timing()
+        sh.close()
+        tile_s = ms / launches / 1e3
+        per_shard.append({"shard": s, "tiles": tiles, "pairs": pairs, "tile_kernel_ms": tile_s * 1e3,
+                          "call_ms": call_s * 1e3})
+        log("shard %d/%d: R %d, %d tiles, tile kernel %.3f ms, call %.3f ms" % (s, G, R, tiles, tile_s * 1e3,
+                                                                             call_s * 1e3))
+        if s == 0:
+            avg0, R0, pairs0, tile0 = call_s, R, pairs, tile_s
+    achieved = FLOP_PER_PAIR * pairs0 / tile0 / 1e12
+    tile_ms = [r["tile_kernel_ms"] for r in per_shard]
+    result = {
+        "metric": "repulsion pair-interactions/s of one GPU's share (shard 0 of %d) at 300K nodes" % G,
+        "value": pairs0 / avg0, "unit": "pair-interactions/s", "n_gpus": 1, "steps": reps,
+        "warmup": max(args.warmup, 10), "ms_per_step": avg0 * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (FP64 Z and cross-tile sums)", "data": "synthetic",
+        "config": {"workload": "shard_300k", "nodes": n, "shards": G, "shard": 0, "tile_rows": R0,
+                   "layout": "N(0, 100 I)", "step": "tsgne_shard_repulsion (tile kernel + Z sum + row sums)"},
+        "roofline": {"bound": "alu", "kernel": "k_repulse (shard 0's tiles)", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic("shard_300k"), "flop_per_launch": FLOP_PER_PAIR * pairs0,
+                     "avg_launch_ms": tile0 * 1e3},
+        "shards": per_shard,
+        "balance_max_over_mean": max(tile_ms) / (sum(tile_ms) / len(tile_ms)),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        T = 64 * R0
+        nb = -(-n // T)
+        a = np.arange(nb)
+        counted = ((np.minimum(a, nb - 1 - a) % G) == 0).astype(np.uint8)
+        group = (np.arange(n) // T).astype(np.int32)
+        Y64 = Y.cpu().numpy().astype(np.float64)
+        sizes = np.minimum(T, n - a * T)
+        rng = np.random.default_rng(3)
+
+        def counted_pairs(rows):
+            k = rows // T
+            per_block = np.array([(counted[np.minimum(b, a)] * sizes).sum() for b in range(nb)])
+            return int((per_block[k] - counted[k]).sum())
+
+        rows = rng.integers(0, n, 64).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.repulsion_terms(Y64, group=group, counted=counted, rows=rows, with_Z=False)
+        dt = time.perf_counter() - t0
+        m = int(min(n, max(64, 64 * args.cpu_seconds / max(dt, 1e-3))))
+        rows = rng.integers(0, n, m).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.repulsion_terms(Y64, group=group, counted=counted, rows=rows, with_Z=False)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": counted_pairs(rows) / dt, "unit": "pair-interactions/s",
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": "FP64 force sums of shard 0 for %d random rows (all their counted "
+                                            "pairs), %.1f s" % (m, dt)}
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def run_knn(args) -> int:
     """The t-SGNE neighbourhood graph G_knn,G (section 2.2, eq. (7)) of the
     300,000-node, 1,000,000-edge graph with k = 90 (three times the default
@@ -481,10 +574,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp, walks or knn")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp, walks, knn or shard")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
     ap.add_argument("--oldest-shares", default="", metavar="LIST",
                     help="serve: extra runs of the same arrivals with these oldest_share values (comma list)")
+    ap.add_argument("--shards", type=int, default=8, help="shard: GPUs the repulsion is split over")
     ap.add_argument("--sparse-nodes", type=int, default=10_000_000, help="sparse: nodes of the SBM")
     ap.add_argument("--n-iter", type=int, default=None, help="optimisation steps per layout (default: workload's)")
     ap.add_argument("--repulsion", default="auto", choices=["auto", "direct", "symmetric"])
@@ -497,8 +591,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the t-SGNE path here is single-GPU (multi-GPU sharding is a design "
-              "note, not built); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only (got --gpus %d): one GPU's share of a repulsion split over N GPUs is "
+              "measured by --workload shard --shards N; the cross-GPU reductions are not built" % args.gpus,
+              file=sys.stderr)
         return 2
 
     import numpy as np
@@ -518,6 +613,8 @@ def main() -> int:
         return run_walks(args)
     if args.workload == "knn":
         return run_knn(args)
+    if args.workload == "shard":
+        return run_shard(args)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

@@ -493,6 +493,68 @@ TSGNE_API tsgne_status tsgne_server_get_stats(tsgne_server* srv, tsgne_server_st
  * frees everything.  NULL is accepted. */
 TSGNE_API tsgne_status tsgne_server_destroy(tsgne_server* srv);
 
+/* ------------------------------------------------------------------------
+ * One GPU's share of a row-sharded repulsion (the repulsive half of the
+ * gradient of eq. (5) and Z of eq. (4)), for runs that spread one graph over
+ * several GPUs.  Positions are cut into nb = ceil(n / T) blocks of T = 64 *
+ * tile_rows; the symmetric tile (a, b), a <= b, holds every pair between
+ * blocks a and b.  Row blocks a and nb-1-a form pair p = min(a, nb-1-a), and
+ * shard s owns the tiles (a, b) whose row block a has p mod n_shards == s
+ * (balanced: a pair of row blocks holds nb+1 tiles).  For its tiles a shard
+ * computes, per node i,
+ *   F_i = sum over pairs {i, j} of its tiles of w_ij^2 (y_i - y_j),
+ *   Z_s = sum over ordered pairs (i, j), i != j, of its tiles of w_ij,
+ * w_ij = (1 + ||y_i - y_j||^2)^-1, with the same tile arithmetic as the
+ * single-GPU step (FP32 per pair; in TSGNE_PREC_SPLIT the cross-tile sums
+ * and Z in FP64).  Summed over all shards, F_i is the repulsive sum R_i and
+ * Z_s is Z, so the gradient is 4 (alpha A_i - R_i / Z) with A from
+ * tsgne_attraction.  Every shard of a run must use the same n, n_shards and
+ * tile_rows.
+ * ------------------------------------------------------------------------ */
+typedef struct tsgne_shard tsgne_shard;
+
+/*
+ * Plans shard `shard` of n_shards for n positions on the current device:
+ * tile_rows 4, 8, 12, 14, 15 or 16, or 0 = chosen from the shard's tile
+ * count.  Allocates the tile list, the partial buffer (nb * nb * T float2:
+ * 8 bytes per node per block) and the Z partials; *out is library-owned,
+ * release it with tsgne_shard_free.  A shard may own no tile (small n, many
+ * shards); its results are then zero.  Synchronising.
+ * Errors: E_INVAL (n < 1, n_shards outside [1, 65536], shard outside
+ * [0, n_shards), bad tile_rows, NULL out), E_NOMEM, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_shard_create(int32_t n, int32_t shard, int32_t n_shards, int32_t tile_rows,
+                                          tsgne_shard** out);
+
+/* The shard's tile rows, tile count and ordered pairs (any may be NULL). */
+TSGNE_API tsgne_status tsgne_shard_info(const tsgne_shard* sh, int32_t* tile_rows, int64_t* tiles, int64_t* pairs);
+
+/*
+ * The shard's force sums and Z partial at layout Y_d (caller-owned device
+ * float32[n][2], read): F_d float64[n][2] (written for every node, zero for
+ * nodes no tile of the shard touches), Z_d float64[1] (written).  precision
+ * TSGNE_PREC_SPLIT or TSGNE_PREC_FP32 (FP32 sums, stored as float64).
+ * Asynchronous on stream; calls on one shard must not overlap (they share its
+ * partial buffer).  Errors: E_INVAL, E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_shard_repulsion(tsgne_shard* sh, const float* Y_d, int32_t precision, double* F_d,
+                                             double* Z_d, void* stream);
+
+/*
+ * Turns event timing of the shard's tile kernel on (enable != 0) or off and
+ * clears the totals.  While on, each tsgne_shard_repulsion brackets its tile
+ * kernel launch with two events on its stream.
+ */
+TSGNE_API tsgne_status tsgne_shard_set_timing(tsgne_shard* sh, int32_t enable);
+
+/* Summed device time (ms) and number of timed tile-kernel launches since
+ * timing was enabled (either may be NULL).  Synchronising (waits for the
+ * last event). */
+TSGNE_API tsgne_status tsgne_shard_timing(tsgne_shard* sh, double* tile_ms, int64_t* launches);
+
+/* Releases a shard (waits for the device first).  NULL is accepted. */
+TSGNE_API tsgne_status tsgne_shard_free(tsgne_shard* sh);
+
 /*
  * Per-phase device timing of one graph's kernels, measured with HIP events
  * recorded on the stream each kernel is launched on.  Phases:

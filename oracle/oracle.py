@@ -25,7 +25,7 @@ _lib = None
 
 __all__ = [
     "build", "lib", "num_threads", "set_threads", "csr_from_edges", "knn_graph", "shortest_path_embedding", "kmeans", "nmi", "aq", "philox4x32_10", "walk_P", "locality_order", "mirror", "edge_sqdist", "calibrate",
-    "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "kl", "kl_given_Z", "update", "run", "OracleError",
+    "symmetrise", "build_P", "Z", "gradient", "gradient_rows", "repulsion_terms", "kl", "kl_given_Z", "update", "run", "OracleError",
 ]
 
 
@@ -71,6 +71,7 @@ def lib():
             "oracle_Z": (dbl, [i32, vp]),
             "oracle_gradient": (None, [i32, vp, vp, vp, vp, dbl, vp, vp]),
             "oracle_gradient_rows": (None, [i32, vp, vp, vp, vp, dbl, vp, i32, vp, vp]),
+            "oracle_repulsion_terms": (None, [i32, vp, vp, vp, vp, i32, vp, vp]),
             "oracle_kl": (dbl, [i32, vp, vp, vp, vp]),
             "oracle_kl_given_Z": (dbl, [i32, vp, vp, vp, vp, dbl]),
             "oracle_update": (None, [i32, vp, vp, vp, vp, dbl, dbl, dbl]),
@@ -287,6 +288,31 @@ def gradient_rows(row_ptr, col, P, Y, rows, alpha: float = 1.0) -> tuple[np.ndar
     lib().oracle_gradient_rows(n, _p(row_ptr), _p(col), _p(P), _p(Y), float(alpha), _p(rows), rows.shape[0],
                                _p(g), ctypes.byref(z))
     return g, z.value
+
+
+def repulsion_terms(Y, group=None, counted=None, rows=None, with_Z: bool = True):
+    """(F float64[rows, 2], Z_part or None): F_i = sum of w_ij^2 (y_i - y_j) and
+    Z_part = sum of w_ij over the pairs {i, j} with counted[min(group[i],
+    group[j])] (all pairs when group is None); w of eq. (4)."""
+    Y = _f64(Y)
+    n = Y.shape[0]
+    if group is not None:
+        group = _i32(group)
+        counted = np.ascontiguousarray(counted, dtype=np.uint8)
+        if group.shape[0] != n or (n and (group.min() < 0 or group.max() >= counted.shape[0])):
+            raise OracleError("group must hold n indices into counted")
+    if rows is not None:
+        rows = _i32(rows)
+        if rows.size and (rows.min() < 0 or rows.max() >= n):
+            raise OracleError("row out of range")
+    nrows = n if rows is None else rows.shape[0]
+    F = np.zeros((max(nrows, 1), 2), np.float64)
+    z = ctypes.c_double(0.0)
+    lib().oracle_repulsion_terms(n, _p(Y), _p(group) if group is not None else None,
+                                 _p(counted) if group is not None else None,
+                                 _p(rows) if rows is not None else None, nrows, _p(F),
+                                 ctypes.byref(z) if with_Z else None)
+    return F[:nrows], (z.value if with_Z else None)
 
 
 def kl(row_ptr, col, P, Y) -> float:

@@ -471,6 +471,54 @@ void oracle_gradient(int32_t n, const int32_t* row_ptr, const int32_t* col, cons
   oracle_gradient_rows(n, row_ptr, col, P, Y, alpha, NULL, n, g, Z_out);
 }
 
+/*
+ * Repulsive sums over a subset of the pairs, to check one share of a run that
+ * splits the pairs between GPUs:
+ *   F_i = sum over counted j != i of w_ij^2 (y_i - y_j),
+ *   Z_part = sum over counted ordered pairs (i, j), i != j, of w_ij
+ * (w of eq. (4); summed over a partition of the pairs, F_i * 4 / Z is the
+ * repulsive half of the gradient and Z_part adds up to Z).  The pair {i, j}
+ * is counted when counted[min(group[i], group[j])] is nonzero; group == NULL
+ * counts every pair.  F is written for the rows listed in `rows` (count
+ * nrows; NULL = all rows, in order); Z_part only when Z_out is not NULL.
+ */
+static int pair_counted(const int32_t* group, const uint8_t* counted, int32_t i, int32_t j) {
+  if (!group) return 1;
+  int32_t gi = group[i], gj = group[j];
+  return counted[gi < gj ? gi : gj] != 0;
+}
+
+void oracle_repulsion_terms(int32_t n, const double* Y, const int32_t* group, const uint8_t* counted,
+                            const int32_t* rows, int32_t nrows, double* F, double* Z_out) {
+  int32_t count = rows ? nrows : n;
+#pragma omp parallel for schedule(static)
+  for (int32_t t = 0; t < count; ++t) {
+    int32_t i = rows ? rows[t] : t;
+    double fx = 0.0, fy = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      if (j == i || !pair_counted(group, counted, i, j)) continue;
+      double w = kernel_w(Y, i, j);
+      fx += w * w * (Y[2 * i] - Y[2 * j]);
+      fy += w * w * (Y[2 * i + 1] - Y[2 * j + 1]);
+    }
+    F[2 * t] = fx;
+    F[2 * t + 1] = fy;
+  }
+  if (!Z_out) return;
+  double* rs = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double z = 0.0;
+    for (int32_t j = 0; j < n; ++j)
+      if (j != i && pair_counted(group, counted, i, j)) z += kernel_w(Y, i, j);
+    rs[i] = z;
+  }
+  double Z = 0.0;
+  for (int32_t i = 0; i < n; ++i) Z += rs[i];
+  free(rs);
+  *Z_out = Z;
+}
+
 /* KL(P || Q) of eq. (5) with q_ij = w_ij / Z for a given Z (the all-pairs
  * sum of oracle_Z at the same Y); terms with p_ij = 0 vanish. */
 double oracle_kl_given_Z(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* P, const double* Y,

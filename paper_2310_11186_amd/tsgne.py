@@ -41,7 +41,8 @@ EXPORTED = (
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
     "tsgne_server_wait", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
-    "tsgne_server_destroy",
+    "tsgne_server_destroy", "tsgne_shard_create", "tsgne_shard_info", "tsgne_shard_repulsion", "tsgne_shard_set_timing",
+    "tsgne_shard_timing", "tsgne_shard_free",
 )
 
 TSGNE_PHASES = ("repulsion", "zsum", "attract", "update", "kl")
@@ -158,6 +159,12 @@ def lib():
             "tsgne_server_cancel": (st, [vp, ctypes.c_uint64]),
             "tsgne_server_get_stats": (st, [vp, ctypes.POINTER(tsgne_server_stats)]),
             "tsgne_server_destroy": (st, [vp]),
+            "tsgne_shard_create": (st, [i32, i32, i32, i32, ctypes.POINTER(vp)]),
+            "tsgne_shard_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+            "tsgne_shard_repulsion": (st, [vp, vp, i32, vp, vp, vp]),
+            "tsgne_shard_set_timing": (st, [vp, i32]),
+            "tsgne_shard_timing": (st, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+            "tsgne_shard_free": (st, [vp]),
             "tsgne_graph_set_timing": (st, [vp, i32]),
             "tsgne_graph_timing": (st, [vp, ctypes.POINTER(tsgne_timing)]),
         }
@@ -385,6 +392,59 @@ class Graph:
         for k in ("col", "mirror", "P"):
             out[k] = out[k][:nnz]
         return out
+
+
+class Shard:
+    """Owns a tsgne_shard*: one GPU's share of a row-sharded repulsion."""
+
+    def __init__(self, n: int, shard: int, n_shards: int, tile_rows: int = 0):
+        h = ctypes.c_void_p(None)
+        _check(lib().tsgne_shard_create(int(n), int(shard), int(n_shards), int(tile_rows), ctypes.byref(h)))
+        self._h = h.value
+        self.n = int(n)
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("shard has been freed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            lib().tsgne_shard_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> tuple[int, int, int]:
+        """(tile rows, tiles, ordered pairs) of this shard."""
+        R, tiles, pairs = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().tsgne_shard_info(self.handle, ctypes.byref(R), ctypes.byref(tiles), ctypes.byref(pairs)))
+        return R.value, tiles.value, pairs.value
+
+    def set_timing(self, enable: bool = True) -> None:
+        _check(lib().tsgne_shard_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self) -> tuple[float, int]:
+        """(total ms, launches) of the tile kernel since timing was enabled (synchronising)."""
+        ms, k = ctypes.c_double(0.0), ctypes.c_int64(0)
+        _check(lib().tsgne_shard_timing(self.handle, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+    def repulsion(self, Y, precision: int = TSGNE_PREC_SPLIT, F=None, Z=None, stream=None):
+        """(F float64[n, 2], Z float64[1]): this shard's force sums and Z partial at Y (float32[n, 2])."""
+        import torch
+        _require(Y, torch.float32, (self.n, 2), "Y")
+        F = torch.empty((self.n, 2), dtype=torch.float64, device=Y.device) if F is None else F
+        Z = torch.empty(1, dtype=torch.float64, device=Y.device) if Z is None else Z
+        _require(F, torch.float64, (self.n, 2), "F")
+        _require(Z, torch.float64, (1,), "Z")
+        _check(lib().tsgne_shard_repulsion(self.handle, _ptr(Y), int(precision), _ptr(F), _ptr(Z), _stream(stream)))
+        return F, Z
 
 
 def tsgne_build_P(row_ptr, col, X, perplexity: float, stream=None) -> Graph:

@@ -92,4 +92,14 @@ def test_argument_validation_before_device_work():
     assert sp(5, 4, dummy, dummy, 3, None, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL                # targets
     assert sp(0, 0, dummy, dummy, 3, dummy, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL               # n < 1
     assert L.tsgne_graph_free(None) == tsgne.TSGNE_OK
+    sh = ctypes.c_void_p(None)
+    for args in [(0, 0, 1, 0), (10, 1, 1, 0), (10, -1, 2, 0), (10, 0, 0, 0), (10, 0, 1, 5), (10, 0, 70000, 0)]:
+        assert L.tsgne_shard_create(*args, ctypes.byref(sh)) == tsgne.TSGNE_E_INVAL
+        assert sh.value is None
+    assert L.tsgne_shard_create(10, 0, 1, 0, None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_shard_repulsion(None, dummy, 0, dummy, dummy, None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_shard_info(None, None, None, None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_shard_set_timing(None, 1) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_shard_timing(None, None, None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_shard_free(None) == tsgne.TSGNE_OK
     assert L.tsgne_status_string(tsgne.TSGNE_E_GRAPH) == b"TSGNE_E_GRAPH"

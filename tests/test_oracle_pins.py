@@ -663,3 +663,63 @@ def test_locality_order_brings_graph_neighbours_together():
     assert np.mean(gap < gi.n // 20) > 2 * np.mean(before < gi.n // 20)
     x = np.random.default_rng(1).standard_normal((50, 12)).astype(np.float32)
     assert np.array_equal(np.sort(oracle.locality_order(x)), np.arange(50))    # d > 8: leading 8 used
+
+
+# ---------------------------------------------------------------------------
+# Repulsive sums over a subset of the pairs (one share of a split run)
+# ---------------------------------------------------------------------------
+
+def test_repulsion_terms_hand_cases():
+    # path (-1,0), (0,0), (1,0): w01 = w12 = 1/2, w02 = 1/5 (eq. (4)), so
+    # F_0 = (1/4)(-1, 0) + (1/25)(-2, 0) = (-33/100, 0), Z = 2 (1/2 + 1/5 + 1/2)
+    Y = np.array([[-1.0, 0.0], [0.0, 0.0], [1.0, 0.0]])
+    F, Z = oracle.repulsion_terms(Y)
+    np.testing.assert_allclose(F, [[-0.33, 0.0], [0.0, 0.0], [0.33, 0.0]], rtol=1e-15, atol=1e-17)
+    assert Z == pytest.approx(2.4, rel=1e-15)
+    # counting only pairs whose lower group is 0, groups (0, 1, 1): {0,1} and
+    # {0,2} count, {1,2} does not: F_1 = (1/4)(1, 0), F_2 = (1/25)(2, 0), Z = 2 (1/2 + 1/5)
+    F, Z = oracle.repulsion_terms(Y, group=[0, 1, 1], counted=[1, 0])
+    np.testing.assert_allclose(F, [[-0.33, 0.0], [0.25, 0.0], [0.08, 0.0]], rtol=1e-15, atol=1e-17)
+    assert Z == pytest.approx(1.4, rel=1e-15)
+    # the complement: only {1,2}
+    F, Z = oracle.repulsion_terms(Y, group=[0, 1, 1], counted=[0, 1])
+    np.testing.assert_allclose(F, [[0.0, 0.0], [-0.25, 0.0], [0.25, 0.0]], rtol=1e-15, atol=1e-17)
+    assert Z == pytest.approx(1.0, rel=1e-15)
+    # unit square: sides w = 1/2, diagonals w = 1/3:
+    # F_0 = (1/4)(-1, 0) + (1/9)(-1, -1) + (1/4)(0, -1) = (-13/36, -13/36)
+    Y = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    F, Z = oracle.repulsion_terms(Y)
+    np.testing.assert_allclose(F[0], [-13 / 36, -13 / 36], rtol=1e-15)
+    assert Z == pytest.approx(16 / 3, rel=1e-15)
+
+
+def test_repulsion_terms_against_gradient_and_invariants():
+    rng = np.random.default_rng(11)
+    n = 150
+    Y = rng.standard_normal((n, 2)) * 4.0
+    F, Z = oracle.repulsion_terms(Y)
+    # with no edges the (finite-difference pinned) gradient is the repulsion alone: g = -4 F / Z
+    row_ptr = np.zeros(n + 1, np.int32)
+    g, Zg = oracle.gradient(row_ptr, np.zeros(0, np.int32), np.zeros(0), Y, 1.0)
+    assert Z == pytest.approx(Zg, rel=1e-13)
+    np.testing.assert_allclose(-4.0 * F / Z, g, rtol=1e-11, atol=1e-15)
+    # a partition of the pairs by lower group adds up to the whole
+    group = np.arange(n) // 16
+    owner = rng.integers(0, 3, size=group.max() + 1)
+    Fs, Zs = np.zeros_like(F), 0.0
+    for s in range(3):
+        Fk, Zk = oracle.repulsion_terms(Y, group=group, counted=(owner == s))
+        # each counted pair acts on both its nodes with opposite forces
+        assert np.abs(Fk.sum(0)).max() < 1e-12 * max(1.0, np.abs(Fk).sum())
+        Fs += Fk
+        Zs += Zk
+    np.testing.assert_allclose(Fs, F, rtol=1e-12, atol=1e-14)
+    assert Zs == pytest.approx(Z, rel=1e-13)
+    # translation invariance and a row subset
+    F2, Z2 = oracle.repulsion_terms(Y + np.array([2.5, -1.0]))
+    np.testing.assert_allclose(F2, F, rtol=1e-9, atol=1e-13)
+    assert Z2 == pytest.approx(Z, rel=1e-12)
+    rows = np.array([149, 3, 77])
+    Fr, Zr = oracle.repulsion_terms(Y, rows=rows, with_Z=False)
+    assert Zr is None
+    np.testing.assert_array_equal(Fr, F[rows])
