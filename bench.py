@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -161,7 +162,8 @@ def run_batch(args) -> int:
 
 def serve_stream(srv_kwargs, reqs, arrivals, n_iter):
     """Submits reqs at the given arrival times (s) and waits for all; returns the
-    server's statistics and the wall time."""
+    server's statistics, the wall time and each request's (latency ms, queued
+    ms) in submission order."""
     from paper_2310_11186_amd import tsgne
     srv = tsgne.Server(**srv_kwargs)
     t0 = time.perf_counter()
@@ -174,15 +176,39 @@ def serve_stream(srv_kwargs, reqs, arrivals, n_iter):
     statuses = [srv.wait(t)[0] for t in tickets]
     wall = time.perf_counter() - t0
     st = srv.stats()
+    times = [srv.latency(t) for t in tickets]
     srv.close()
     if any(s != tsgne.TSGNE_OK for s in statuses):
         raise RuntimeError("a served request failed: %s" % statuses)
+    st["per_request"] = times
     return st, wall
 
 
+def nearest_rank(values, q):
+    """The q-quantile by nearest rank (the server's own definition)."""
+    v = sorted(values)
+    return v[min(len(v), max(1, math.ceil(q * len(v)))) - 1] if v else None
+
+
+def by_size_decile(reqs, st):
+    """p50 / max latency (ms) of the requests in each tenth of the node counts."""
+    order = sorted(range(len(reqs)), key=lambda k: reqs[k].n)
+    out = []
+    for d in range(10):
+        idx = order[d * len(order) // 10:(d + 1) * len(order) // 10]
+        if not idx:
+            continue
+        lat = [st["per_request"][k][0] for k in idx]
+        out.append({"decile": d + 1, "nodes": [reqs[idx[0]].n, reqs[idx[-1]].n], "requests": len(idx),
+                    "latency_p50_ms": nearest_rank(lat, 0.5), "latency_max_ms": max(lat)})
+    return out
+
+
 def run_serve(args) -> int:
-    """Serving: layout requests with Poisson arrivals at 0.8x the measured
-    saturated rate, continuous batching against one request at a time."""
+    """Serving: layout requests with Poisson arrivals at fractions of the
+    measured saturated rate (0.8 is the headline), continuous batching against
+    one request at a time, latency by request size, and a run under a small
+    device-memory budget that makes requests queue for memory."""
     import numpy as np
 
     from paper_2310_11186_amd import synth, tsgne
@@ -200,22 +226,44 @@ def run_serve(args) -> int:
     log("saturated: %.2f layouts/s" % sat_rate)
     st_sat1, wall_sat1 = serve_stream(kw1, reqs, [0.0] * count, n_iter)
     log("saturated, one at a time: %.2f layouts/s" % (count / wall_sat1))
+
+    def arrivals_at(frac):
+        rng = np.random.default_rng(2310_11186)
+        return np.cumsum(rng.exponential(1.0 / (frac * sat_rate), size=count))
+
+    def summary(st, wall):
+        return {"layouts_per_s": count / wall, "latency_p50_ms": st["latency_p50_ms"],
+                "latency_p99_ms": st["latency_p99_ms"], "latency_mean_ms": st["latency_mean_ms"],
+                "queued_max_ms": max(q for _, q in st["per_request"]), "seconds": wall}
+
     qps = 0.8 * sat_rate
-    rng = np.random.default_rng(2310_11186)
-    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=count))
+    arrivals = arrivals_at(0.8)
     st, wall = serve_stream(kw, reqs, arrivals, n_iter)
     log("served at %.2f req/s: p50 %.0f ms, p99 %.0f ms" % (qps, st["latency_p50_ms"], st["latency_p99_ms"]))
     st1, wall1 = serve_stream(kw1, reqs, arrivals, n_iter)
     log("one at a time: p50 %.0f ms, p99 %.0f ms" % (st1["latency_p50_ms"], st1["latency_p99_ms"]))
     st_eq, wall_eq = serve_stream(dict(kw, oldest_share=0.0), reqs, arrivals, n_iter)
     log("equal shares: p50 %.0f ms, p99 %.0f ms" % (st_eq["latency_p50_ms"], st_eq["latency_p99_ms"]))
+    load = []
+    for frac in [float(v) for v in args.qps_fractions.split(",") if v]:
+        if frac == 0.8:
+            rec = summary(st, wall)
+        else:
+            st_f, wall_f = serve_stream(kw, reqs, arrivals_at(frac), n_iter)
+            rec = summary(st_f, wall_f)
+        load.append(dict(rec, fraction_of_saturated=frac, qps=frac * sat_rate))
+        log("load %.2f x saturated: p50 %.0f ms, p99 %.0f ms" % (frac, rec["latency_p50_ms"], rec["latency_p99_ms"]))
+    low = None
+    if args.serve_low_budget_mb:
+        st_lb, wall_lb = serve_stream(dict(kw, hbm_budget=args.serve_low_budget_mb << 20), reqs, arrivals, n_iter)
+        low = dict(summary(st_lb, wall_lb), hbm_budget_mb=args.serve_low_budget_mb)
+        log("budget %d MiB: p50 %.0f ms, p99 %.0f ms, longest wait for memory %.0f ms" %
+            (args.serve_low_budget_mb, low["latency_p50_ms"], low["latency_p99_ms"], low["queued_max_ms"]))
     sweep = []
     for share in [float(v) for v in args.oldest_shares.split(",") if v]:
         st_s, wall_s = serve_stream(dict(kw, oldest_share=share), reqs, arrivals, n_iter)
         log("oldest share %.2f: p50 %.0f ms, p99 %.0f ms" % (share, st_s["latency_p50_ms"], st_s["latency_p99_ms"]))
-        sweep.append({"oldest_share": share, "latency_p50_ms": st_s["latency_p50_ms"],
-                      "latency_p99_ms": st_s["latency_p99_ms"], "latency_mean_ms": st_s["latency_mean_ms"],
-                      "seconds": wall_s})
+        sweep.append(dict(summary(st_s, wall_s), oldest_share=share))
     pairs = sum(float(gi.n) * (gi.n - 1) for gi in reqs) * n_iter
     result = {
         "metric": "served layouts/s with p50/p99 latency (Poisson arrivals, continuous batching)",
@@ -232,11 +280,14 @@ def run_serve(args) -> int:
         "saturated": {"layouts_per_s": sat_rate, "seconds": wall_sat,
                       "one_at_a_time_layouts_per_s": count / wall_sat1,
                       "speedup_vs_one_at_a_time": wall_sat1 / wall_sat},
-        "one_at_a_time": {"layouts_per_s": count / wall1, "latency_p50_ms": st1["latency_p50_ms"],
-                          "latency_p99_ms": st1["latency_p99_ms"], "seconds": wall1},
-        "equal_shares": {"layouts_per_s": count / wall_eq, "latency_p50_ms": st_eq["latency_p50_ms"],
-                         "latency_p99_ms": st_eq["latency_p99_ms"], "seconds": wall_eq},
+        "one_at_a_time": summary(st1, wall1),
+        "equal_shares": summary(st_eq, wall_eq),
+        "by_size_decile": by_size_decile(reqs, st),
+        "by_size_decile_one_at_a_time": by_size_decile(reqs, st1),
+        "by_load": load,
     }
+    if low:
+        result["low_budget"] = low
     if sweep:
         result["oldest_share_sweep"] = sweep
     print(json.dumps(result), flush=True)
@@ -576,6 +627,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, batch256, serve, sparse, sp, walks, knn or shard")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
+    ap.add_argument("--qps-fractions", default="0.5,0.8,0.95", metavar="LIST",
+                    help="serve: Poisson arrival rates as fractions of the saturated rate (comma list)")
+    ap.add_argument("--serve-low-budget-mb", type=int, default=512, metavar="MIB",
+                    help="serve: device-memory budget of the low-budget run (0 = skip it)")
     ap.add_argument("--oldest-shares", default="", metavar="LIST",
                     help="serve: extra runs of the same arrivals with these oldest_share values (comma list)")
     ap.add_argument("--shards", type=int, default=8, help="shard: GPUs the repulsion is split over")

@@ -481,6 +481,12 @@ TSGNE_API tsgne_status tsgne_server_poll(tsgne_server* srv, uint64_t ticket, flo
 /* Blocks until the request has finished; outputs as tsgne_server_poll. */
 TSGNE_API tsgne_status tsgne_server_wait(tsgne_server* srv, uint64_t ticket, float* Y_h, tsgne_status* result);
 
+/* Times of a finished request that has not been released (either pointer may
+ * be NULL): *latency_ms from submission to completion, *queued_ms from
+ * submission to admission (to completion for a request cancelled while
+ * queued).  E_INVAL for an unknown ticket, E_BUSY while queued or running. */
+TSGNE_API tsgne_status tsgne_server_latency(tsgne_server* srv, uint64_t ticket, double* latency_ms, double* queued_ms);
+
 /* Forgets a finished request (its layout copy is released).  E_BUSY if running. */
 TSGNE_API tsgne_status tsgne_server_release(tsgne_server* srv, uint64_t ticket);
 

@@ -41,7 +41,8 @@ struct Request {
   std::vector<int32_t> edges;
   std::vector<float> X, Y0, Y;
   size_t footprint = 0;
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_admit, t_done;
+  bool admitted = false;
   bool done = false, cancel = false;
   tsgne_status status = TSGNE_OK;
   std::string error;
@@ -219,6 +220,8 @@ void tsgne_server::admit(hipStream_t s) {
       r = queue.front();
       queue.pop_front();
       hbm_used += r->footprint;
+      r->t_admit = Clock::now();
+      r->admitted = true;
     }
     Slot sl;
     sl.req = r;
@@ -533,6 +536,18 @@ tsgne_status tsgne_server_wait(tsgne_server* srv, uint64_t ticket, float* Y_h, t
   srv->cv_done.wait(lk, [&] { return r->done; });
   if (result) *result = r->status;
   if (Y_h && r->status == TSGNE_OK) std::copy(r->Y.begin(), r->Y.end(), Y_h);
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_latency(tsgne_server* srv, uint64_t ticket, double* latency_ms, double* queued_ms) {
+  if (!srv) return fail(TSGNE_E_INVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  const Request& r = *it->second;
+  if (!r.done) return fail(TSGNE_E_BUSY, "request still queued or running");
+  if (latency_ms) *latency_ms = 1e3 * seconds_since(r.t_submit, r.t_done);
+  if (queued_ms) *queued_ms = 1e3 * seconds_since(r.t_submit, r.admitted ? r.t_admit : r.t_done);
   return TSGNE_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTED = (
     "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
-    "tsgne_server_wait", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
+    "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
     "tsgne_server_destroy", "tsgne_shard_create", "tsgne_shard_info", "tsgne_shard_repulsion", "tsgne_shard_set_timing",
     "tsgne_shard_timing", "tsgne_shard_free",
 )
@@ -155,6 +155,8 @@ def lib():
             "tsgne_server_submit": (st, [vp, ctypes.POINTER(tsgne_request), ctypes.POINTER(ctypes.c_uint64)]),
             "tsgne_server_poll": (st, [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "tsgne_server_wait": (st, [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32)]),
+            "tsgne_server_latency": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
             "tsgne_server_release": (st, [vp, ctypes.c_uint64]),
             "tsgne_server_cancel": (st, [vp, ctypes.c_uint64]),
             "tsgne_server_get_stats": (st, [vp, ctypes.POINTER(tsgne_server_stats)]),
@@ -618,6 +620,12 @@ class Server:
         st = ctypes.c_int32(0)
         _check(lib().tsgne_server_wait(self._h, ticket, Y.ctypes.data, ctypes.byref(st)))
         return st.value, (Y if st.value == TSGNE_OK else None)
+
+    def latency(self, ticket: int) -> tuple[float, float]:
+        """(submission to completion, submission to admission) in ms of a finished request."""
+        lat, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(lib().tsgne_server_latency(self._h, ticket, ctypes.byref(lat), ctypes.byref(q)))
+        return lat.value, q.value
 
     def cancel(self, ticket: int) -> None:
         _check(lib().tsgne_server_cancel(self._h, ticket))

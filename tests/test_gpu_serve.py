@@ -2,6 +2,8 @@
 the same alone and in the mix, admission by memory budget queues requests,
 and failures (non-finite input, cancellation, oversize, full queue) stay
 with the request that caused them."""
+import math
+
 import numpy as np
 import pytest
 
@@ -48,9 +50,19 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
     tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
     outs = [srv.wait(t) for t in tickets]
     st = srv.stats()
+    times = [srv.latency(t) for t in tickets]
     srv.close()
     assert st["completed"] == len(gis) and st["failed"] == 0
     assert st["latency_p99_ms"] >= st["latency_p50_ms"] > 0 and st["layouts_per_s"] > 0
+    # per-request times: queued <= latency; the nearest-rank percentiles and the
+    # mean of the per-request latencies are the server's statistics
+    lat = sorted(t[0] for t in times)
+    assert all(0.0 <= q <= l for l, q in times)
+    assert lat[math.ceil(0.5 * len(lat)) - 1] == st["latency_p50_ms"]
+    assert lat[min(len(lat), math.ceil(0.99 * len(lat))) - 1] == st["latency_p99_ms"]
+    assert sum(lat) / len(lat) == pytest.approx(st["latency_mean_ms"], rel=1e-12)
+    if max_active < len(gis) or budget:
+        assert max(q for _, q in times) > 0.0   # someone waited for a slot or for memory
     for gi, k, (status, Y) in zip(gis, iters, outs):
         assert status == tsgne.TSGNE_OK
         assert np.array_equal(Y, alone(gi, k, 4, gpu)), gi.n
@@ -89,6 +101,12 @@ def test_failures_stay_with_their_request(gpu):
     status_long, _ = srv.wait(long_t)
     assert status_bad == tsgne.TSGNE_E_NONFINITE
     assert status_long == tsgne.TSGNE_E_CANCELLED
+    lat, q = srv.latency(long_t)
+    assert 0.0 <= q <= lat
+    srv.release(long_t)
+    with pytest.raises(tsgne.TsgneError) as e:
+        srv.latency(long_t)
+    assert e.value.status == tsgne.TSGNE_E_INVAL
     for gi, k, t in zip(gis[:3], iters[:3], good):
         status, Y = srv.wait(t)
         assert status == tsgne.TSGNE_OK
@@ -124,6 +142,9 @@ def test_oversize_and_full_queue(gpu):
             assert err.status == tsgne.TSGNE_E_BUSY
             busy += 1
     assert busy >= 1
+    with pytest.raises(tsgne.TsgneError) as e:
+        srv.latency(t0)   # queued or running
+    assert e.value.status == tsgne.TSGNE_E_BUSY
     srv.cancel(t0)
     for t in extra:
         srv.cancel(t)
