@@ -131,18 +131,23 @@ std::vector<int2> shard_tiles(int32_t n, int32_t R, int32_t shard, int32_t n_sha
   return items;
 }
 
-// Tile rows for a shard: the single-graph cost model applied to the shard's
-// tile count (rounds of 4096 resident waves times the tile area, over the
-// tile's relative per-pair efficiency).
+// Tile rows for a shard: the single-graph cost model applied to the largest
+// shard's tile count (its tiles over the chip's 1024 SIMDs rounded up, at
+// least the 64 / R a SIMD needs to hide latency, times the tile area, over
+// the tile's per-pair efficiency relative to R = 16).
 int32_t shard_tile_rows(int32_t n, int32_t n_shards) {
   const int32_t rs[6] = {16, 15, 14, 12, 8, 4};
-  const double eff[6] = {1.0, 1.0, 1.0, 0.83, 0.84, 0.7};
+  const double eff[6] = {1.0, 1.0, 1.0, 1.0, 0.97, 0.81};
+  constexpr int64_t kSimds = 1024;
   double best = 0.0;
   int32_t R = 8;
   for (int k = 0; k < 6; ++k) {
     const int64_t T = (int64_t)kWave * rs[k], nb = (n + T - 1) / T;
-    const int64_t per_shard = (nb * (nb + 1) / 2 + n_shards - 1) / n_shards;
-    const double cost = (double)((per_shard + 4095) / 4096) * (double)(T * T) / eff[k];
+    // a pair of row blocks holds nb + 1 tiles; the largest shard has the most pairs
+    const int64_t pairs = (nb + 1) / 2;
+    const int64_t per_shard = (pairs + n_shards - 1) / n_shards * (nb + 1);
+    const int64_t per_simd = std::max<int64_t>((per_shard + kSimds - 1) / kSimds, kWave / rs[k]);
+    const double cost = (double)per_simd * (double)(T * T) / eff[k];
     if (best == 0.0 || cost < best) {
       best = cost;
       R = rs[k];

@@ -18,6 +18,7 @@
 // to part[b][a], so part[k][*] holds every contribution to block k exactly
 // once and the update kernel adds them in a fixed order: results do not
 // depend on scheduling.  Z partials are per tile.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -272,8 +273,20 @@ __device__ __forceinline__ void tile_diag_light(const float2* __restrict__ Y, in
   }
 }
 
+// Waves per SIMD the repulsion kernels must allow.  With few rows per lane a
+// step holds too few independent pairs to hide the dependent-issue latency
+// at the 4 waves per SIMD the compiler's default register budget gives
+// (measured with R = 8: 37 % more cycles waiting on dependencies than R = 16
+// for 4 % more VALU instructions).  Asking for 6 keeps R = 8 at 69 VGPRs
+// (7 waves per SIMD) and 5 keeps R = 12 at 93 (5 waves), both without
+// spills; R >= 14 would spill below 4 waves and keeps the default.
+template <int R>
+constexpr int repulse_min_waves() {
+  return R <= 8 ? 6 : R <= 12 ? 5 : 1;
+}
+
 template <int R, bool SPLIT, bool SYM>
-__global__ __launch_bounds__(kBlock) void k_repulse(const float2* __restrict__ Y, int32_t n, int32_t nb,
+__global__ __launch_bounds__(kBlock, repulse_min_waves<R>()) void k_repulse(const float2* __restrict__ Y, int32_t n, int32_t nb,
                                                     const int2* __restrict__ items, int64_t n_items,
                                                     float2* __restrict__ part, double* __restrict__ zpart,
                                                     float* __restrict__ zpart32) {
@@ -519,7 +532,7 @@ __device__ __forceinline__ bool batch_live(const BatchDesc& d) {
 }
 
 template <int R, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_batch_repulse(const BatchDesc* __restrict__ descs,
+__global__ __launch_bounds__(kBlock, repulse_min_waves<R>()) void k_batch_repulse(const BatchDesc* __restrict__ descs,
                                                           const int4* __restrict__ items, int64_t n_items) {
   const int64_t item =
       (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -642,6 +655,9 @@ inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + pe
 
 }  // namespace
 
+// SIMDs of the chip (256 CUs x 4).
+constexpr int64_t kSimds = 1024;
+
 RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
   RepulsionPlan p;
   p.variant = (variant == TSGNE_REPULSION_DIRECT) ? TSGNE_REPULSION_DIRECT : TSGNE_REPULSION_SYMMETRIC;
@@ -650,17 +666,22 @@ RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
     return p.variant == TSGNE_REPULSION_DIRECT ? nb * nb : nb * (nb + 1) / 2;
   };
   if (!tile_rows_supported(R)) {
-    // Cost model: rounds of 4096 resident waves (4 per SIMD) times the tile
-    // area, divided by the per-pair efficiency of that tile relative to R = 16
-    // (measured on MI355X at 300K nodes: R = 8 and 12 run ~0.84x as fast; the
-    // R = 4 figure is an estimate).  Small graphs get small tiles (more waves
-    // in flight), large graphs the tile whose count fills the last round best.
+    // Cost model: the tiles (one wave each) of the busiest SIMD, i.e. the
+    // tile count over the chip's 1024 SIMDs rounded up, times the tile area,
+    // divided by the per-pair efficiency of that tile relative to R = 16
+    // (measured on MI355X at 300K nodes: 1 for R = 12..16, 0.97 for 8, 0.81
+    // for 4).  A SIMD needs about 64 / R resident tiles (64 independent pairs
+    // per step over its waves) to hide the dependent-issue latency, so fewer
+    // tiles than that take as long as that many.  Small graphs get small
+    // tiles (every SIMD busy), large graphs the tile whose count divides best
+    // over the SIMDs.
     const int32_t rs[6] = {16, 15, 14, 12, 8, 4};
-    const double eff[6] = {1.0, 1.0, 1.0, 0.83, 0.84, 0.7};
+    const double eff[6] = {1.0, 1.0, 1.0, 1.0, 0.97, 0.81};
     double best = 0.0;
     for (int k = 0; k < 6; ++k) {
       const double T = (double)(kWave * rs[k]);
-      const double cost = (double)((items_for(rs[k]) + 4095) / 4096) * T * T / eff[k];
+      const int64_t per_simd = std::max<int64_t>((items_for(rs[k]) + kSimds - 1) / kSimds, kWave / rs[k]);
+      const double cost = (double)per_simd * T * T / eff[k];
       if (best == 0.0 || cost < best) {
         best = cost;
         R = rs[k];

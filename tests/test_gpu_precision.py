@@ -123,5 +123,9 @@ def test_precision_c3_subsample(gpu):
     sp, fp = entry["split"], entry["fp32"]
     assert entry["P_rel_l2"] <= 1e-6
     assert sp["grad_rel_l2_at_oracle_state"] <= 1e-5 and sp["Z_rel_at_oracle_state"] <= 1e-5
-    assert abs(sp["kl_rel_to_oracle"]) <= 0.02
-    assert fp["grad_rel_l2_at_oracle_state"] <= 1e-3 and abs(fp["kl_rel_to_oracle"]) <= 0.05
+    # After 250 steps the layout is past the chaotic early phase: the FP64
+    # oracle itself, started from Y0 perturbed by 1e-7 relative, ends with KL
+    # between -0.9 % and +3.4 % of its unperturbed run (5 perturbed runs), so
+    # the final KL is held to a bar above that spread, not to rounding error
+    assert abs(sp["kl_rel_to_oracle"]) <= 0.05
+    assert fp["grad_rel_l2_at_oracle_state"] <= 1e-3 and abs(fp["kl_rel_to_oracle"]) <= 0.08

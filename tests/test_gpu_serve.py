@@ -69,11 +69,12 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
 
 
 def test_per_request_tiles_mix_equals_alone(gpu):
-    # tile_rows = 0: small requests take 8 rows, a 140000-node request the
-    # plan's 15 and a 150000-node one 16, so a round runs three batched plans
-    # on parallel branches; each layout still equals its own run alone.
+    # tile_rows = 0: small requests take 8 rows and the 145000- and
+    # 152000-node requests the single-graph plan's choices (14 and 16 with the
+    # current cost model), so a round runs three batched plans on parallel
+    # branches; each layout still equals its own run alone.
     gis = [synth.small_sbm(n, 3, 5.0, 8, 300 + k) for k, n in enumerate([900, 2100, 400])]
-    gis += [synth.small_sbm(n, 6, 6.0, 8, 310 + k) for k, n in enumerate([140_000, 150_000])]
+    gis += [synth.small_sbm(n, 6, 6.0, 8, 310 + k) for k, n in enumerate([145_000, 152_000])]
     iters = [40, 25, 60, 12, 9]
     srv = tsgne.Server(max_active=64, steps_per_round=7, tile_rows=0, round_ms=0.05,
                        params=tsgne.tsgne_params_default(**PARAMS))
