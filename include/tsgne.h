@@ -26,6 +26,11 @@
  *  - A tsgne_graph* is owned by the library; release it with tsgne_graph_free.
  *    Calls on one graph must not overlap (they share its workspace); different
  *    graphs may be used concurrently from different threads.
+ *  - Device memory of the step workspace (allocated on the first step,
+ *    gradient or run): the repulsion partials take 8 * n * nb bytes, nb =
+ *    ceil(n / (64 * tile_rows)) (about 0.8 GB at 300K nodes, 31 GB at 2M with
+ *    16 rows per lane), plus about 40 bytes per node and 8 per tile; a graph
+ *    whose workspace does not fit fails with E_NOMEM.
  */
 #ifndef TSGNE_H
 #define TSGNE_H
