@@ -150,7 +150,10 @@ def states(n, seed):
     ("dcsbm", 3001, 16, tsgne.TSGNE_REPULSION_SYMMETRIC),
     ("dcsbm", 3001, 15, tsgne.TSGNE_REPULSION_SYMMETRIC),
     ("dcsbm", 3001, 14, tsgne.TSGNE_REPULSION_SYMMETRIC),
+    ("dcsbm", 3001, 12, tsgne.TSGNE_REPULSION_SYMMETRIC),
     ("dcsbm", 3001, 12, tsgne.TSGNE_REPULSION_DIRECT),
+    ("dcsbm", 3001, 16, tsgne.TSGNE_REPULSION_DIRECT),
+    ("dcsbm", 3001, 4, tsgne.TSGNE_REPULSION_DIRECT),
     ("dcsbm", 3001, 8, tsgne.TSGNE_REPULSION_DIRECT),
     ("sbm2k", 2000, 0, tsgne.TSGNE_REPULSION_AUTO),
 ])
