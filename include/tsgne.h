@@ -302,6 +302,23 @@ TSGNE_API tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t
                                            const float* X_d, int32_t d, int32_t walks, int32_t length, uint64_t seed,
                                            void* stream, tsgne_graph** out);
 
+/*
+ * A graph whose joint affinities P are given instead of built: the CSR
+ * (row_ptr_h int32[n+1], col_h int32[nnz], host, canonical and symmetric as
+ * for tsgne_build_P) and P_h float32[nnz] (host, aligned with col_h) are
+ * copied in.  P plays the role of eq. (3)'s joint affinities: it must be
+ * finite, non-negative and symmetric entry by entry (p_ij == p_ji bitwise);
+ * it should sum to one (not checked).  Meant for checking the optimisation
+ * loop on affinities computed elsewhere (e.g. a reference implementation's
+ * P rounded to FP32).  The graph's beta (tsgne_graph_export) reads 0.
+ * Synchronising.  *out is library-owned; release it with tsgne_graph_free.
+ * Errors: E_INVAL (sizes, null pointers, P not finite, negative or not
+ * symmetric), E_GRAPH (CSR not canonical or not symmetric), E_NOMEM,
+ * E_DEVICE.
+ */
+TSGNE_API tsgne_status tsgne_graph_from_host_P(int32_t n, int64_t nnz, const int32_t* row_ptr_h, const int32_t* col_h,
+                                               const float* P_h, void* stream, tsgne_graph** out);
+
 /* Releases a graph and all device memory it holds.  NULL is accepted. */
 TSGNE_API tsgne_status tsgne_graph_free(tsgne_graph* g);
 

@@ -493,6 +493,57 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
   return TSGNE_OK;
 }
 
+tsgne_status tsgne_graph_from_host_P(int32_t n, int64_t nnz, const int32_t* row_ptr_h, const int32_t* col_h,
+                                     const float* P_h, void* stream, tsgne_graph** out) {
+  if (!out) return fail(TSGNE_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1) return fail(TSGNE_E_INVAL, "n must be >= 1");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return fail(TSGNE_E_INVAL, "nnz must lie in [0, 2^31)");
+  if (!row_ptr_h || (nnz > 0 && (!col_h || !P_h))) return fail(TSGNE_E_INVAL, "null pointer");
+  if (row_ptr_h[0] != 0 || row_ptr_h[n] != nnz) return fail(TSGNE_E_GRAPH, "row_ptr must span [0, nnz]");
+  for (int64_t e = 0; e < nnz; ++e)
+    if (!std::isfinite(P_h[e]) || P_h[e] < 0.f) return fail(TSGNE_E_INVAL, "P must be finite and >= 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int32_t* rp_d = nullptr;
+  int32_t* col_d = nullptr;
+  struct Upload {
+    int32_t*& rp;
+    int32_t*& col;
+    ~Upload() {
+      dfree(rp);
+      dfree(col);
+    }
+  } upload{rp_d, col_d};
+  TSGNE_HIP(dalloc(&rp_d, (size_t)n + 1), "allocate row_ptr");
+  TSGNE_HIP(dalloc(&col_d, (size_t)nnz), "allocate col");
+  TSGNE_HIP(hipMemcpyAsync(rp_d, row_ptr_h, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s),
+            "upload row_ptr");
+  if (nnz > 0)
+    TSGNE_HIP(hipMemcpyAsync(col_d, col_h, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s), "upload col");
+  tsgne_graph* g = nullptr;
+  if (tsgne_status st = graph_structure(n, nnz, rp_d, col_d, s, &g)) return st;
+  struct Cleanup {
+    tsgne_graph* g;
+    ~Cleanup() { free_graph(g); }
+  } guard{g};
+  // the CSR is canonical and symmetric now: P must be too (p_ij = p_ji)
+  for (int32_t i = 0; i < n; ++i) {
+    for (int64_t e = row_ptr_h[i]; e < row_ptr_h[i + 1]; ++e) {
+      const int32_t j = col_h[e];
+      const int32_t* first = col_h + row_ptr_h[j];
+      const int32_t* hit = std::lower_bound(first, col_h + row_ptr_h[j + 1], i);
+      if (P_h[e] != P_h[row_ptr_h[j] + (hit - first)]) return fail(TSGNE_E_INVAL, "P must be symmetric");
+    }
+  }
+  if (nnz > 0)
+    TSGNE_HIP(hipMemcpyAsync(g->P, P_h, sizeof(float) * (size_t)nnz, hipMemcpyHostToDevice, s), "upload P");
+  TSGNE_HIP(hipMemsetAsync(g->beta, 0, sizeof(double) * (size_t)n, s), "clear beta");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise graph_from_host_P");
+  guard.g = nullptr;
+  *out = g;
+  return TSGNE_OK;
+}
+
 tsgne_status tsgne_graph_free(tsgne_graph* g) {
   free_graph(g);
   return TSGNE_OK;

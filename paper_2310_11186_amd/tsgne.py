@@ -37,7 +37,7 @@ EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
     "tsgne_build_P_walks", "tsgne_locality_order", "tsgne_permute_graph", "tsgne_permute_rows",
-    "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
+    "tsgne_graph_from_host_P", "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
     "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
@@ -139,6 +139,7 @@ def lib():
             "tsgne_locality_order": (st, [i32, vp, i32, vp, vp]),
             "tsgne_permute_graph": (st, [i32, i64, vp, vp, vp, vp, vp, vp]),
             "tsgne_permute_rows": (st, [i32, i32, vp, vp, i32, vp, vp]),
+            "tsgne_graph_from_host_P": (st, [i32, i64, vp, vp, vp, vp, ctypes.POINTER(vp)]),
             "tsgne_graph_free": (st, [vp]),
             "tsgne_graph_info": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
             "tsgne_graph_export": (st, [vp, vp, vp, vp, vp, vp]),
@@ -461,6 +462,21 @@ def tsgne_build_P(row_ptr, col, X, perplexity: float, stream=None) -> Graph:
     h = ctypes.c_void_p(None)
     _check(lib().tsgne_build_P(n, col.shape[0], _ptr(row_ptr), _ptr(col) if col.numel() else None, _ptr(X),
                                X.shape[1], float(perplexity), _stream(stream), ctypes.byref(h)))
+    return Graph(h.value)
+
+
+def tsgne_graph_from_host_P(row_ptr, col, P, stream=None) -> Graph:
+    """A graph with given joint affinities: row_ptr int32[n+1], col int32[nnz]
+    (canonical symmetric CSR) and P float32[nnz] (symmetric), host numpy arrays."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    P = np.ascontiguousarray(P, np.float32)
+    if P.shape != col.shape:
+        raise ValueError("P must be aligned with col")
+    h = ctypes.c_void_p(None)
+    _check(lib().tsgne_graph_from_host_P(row_ptr.shape[0] - 1, col.shape[0], row_ptr.ctypes.data,
+                                         col.ctypes.data if col.size else None, P.ctypes.data if P.size else None,
+                                         _stream(stream), ctypes.byref(h)))
     return Graph(h.value)
 
 

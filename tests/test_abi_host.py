@@ -92,6 +92,20 @@ def test_argument_validation_before_device_work():
     assert sp(5, 4, dummy, dummy, 3, None, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL                # targets
     assert sp(0, 0, dummy, dummy, 3, dummy, 2.0, dummy, None, None) == tsgne.TSGNE_E_INVAL               # n < 1
     assert L.tsgne_graph_free(None) == tsgne.TSGNE_OK
+    # given-P graphs: sizes, the row_ptr span and P's values are checked on the host
+    rp = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    good = np.array([0.5, 0.5], np.float32)
+    fhp = L.tsgne_graph_from_host_P
+    assert fhp(0, 0, rp.ctypes.data, col.ctypes.data, good.ctypes.data, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert fhp(2, -1, rp.ctypes.data, col.ctypes.data, good.ctypes.data, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert fhp(2, 2, rp.ctypes.data, col.ctypes.data, None, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert fhp(2, 2, rp.ctypes.data, col.ctypes.data, good.ctypes.data, None, None) == tsgne.TSGNE_E_INVAL
+    assert fhp(2, 3, rp.ctypes.data, col.ctypes.data, good.ctypes.data, None, ctypes.byref(out)) == tsgne.TSGNE_E_GRAPH
+    for bad in ([-0.5, 0.5], [float("nan"), 0.5], [float("inf"), 0.5]):
+        b = np.array(bad, np.float32)
+        assert fhp(2, 2, rp.ctypes.data, col.ctypes.data, b.ctypes.data, None, ctypes.byref(out)) == tsgne.TSGNE_E_INVAL
+    assert out.value is None
     sh = ctypes.c_void_p(None)
     for args in [(0, 0, 1, 0), (10, 1, 1, 0), (10, -1, 2, 0), (10, 0, 0, 0), (10, 0, 1, 5), (10, 0, 70000, 0)]:
         assert L.tsgne_shard_create(*args, ctypes.byref(sh)) == tsgne.TSGNE_E_INVAL
