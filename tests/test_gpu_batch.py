@@ -80,3 +80,37 @@ def test_batch_rejects_bad_arguments(gpu):
     assert e.value.status == tsgne.TSGNE_E_INVAL
     with pytest.raises(tsgne.TsgneError):
         tsgne.tsgne_batch_run([g], [Y], [-1], p)
+
+
+def test_full_batch_workload_sampled(gpu):
+    """The benchmark's whole batch (256 graphs, 2.94M nodes) in its own launch
+    configuration (the autotuner's tile): 8 batched steps, then the smallest,
+    a middle and the largest graph run alone with the same tile must end
+    bitwise equal, and the smallest matches the FP64 oracle."""
+    import torch
+    gis = synth.batch_workload()
+    graphs = [upload(gi, gpu) for gi in gis]
+    steps = 8
+    params = tsgne.tsgne_params_default(exaggeration_iters=187)
+    Y0 = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    best, _ = tsgne.tsgne_autotune(graphs, Y0, params, steps=2)
+    p = tsgne.tsgne_params_default(exaggeration_iters=187, tile_rows=best)
+    Yb = [y.clone() for y in Y0]
+    tsgne.tsgne_batch_run(graphs, Yb, [steps] * len(gis), p)
+    order = sorted(range(len(gis)), key=lambda k: gis[k].n)
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        Ya = Y0[k].clone()
+        tsgne.tsgne_run(graphs[k], Ya, steps, tsgne.tsgne_params_default(
+            exaggeration_iters=187, tile_rows=best, repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC))
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yb[k]), gis[k].n
+    k = order[0]
+    gi = gis[k]
+    rp, col = oracle.csr_from_edges(gi.n, gi.edges)
+    P, _ = oracle.build_P(rp, col, gi.X, 30.0)
+    eta = float(np.float32(max(np.float32(gi.n) / np.float32(48.0), np.float32(50.0))))   # the automatic rate
+    oY, _, _, _ = oracle.run(rp, col, P, gi.Y0, n_steps=steps, exaggeration_iters=187, eta=eta)
+    err = np.linalg.norm(Yb[k].cpu().numpy() - oY) / np.linalg.norm(oY)
+    assert err <= 1e-4, (gi.n, err)
+    for g in graphs:
+        g.close()

@@ -150,3 +150,32 @@ def test_oversize_and_full_queue(gpu):
     for t in extra:
         srv.cancel(t)
     srv.close()
+
+
+def test_full_serving_stream_sampled(gpu):
+    """The benchmark's 48-request stream (1K-200K nodes) through the server with
+    its default configuration (per-request tiles, 25 ms rounds), all submitted
+    at once and cut to 12 iterations: the smallest, a middle and the largest
+    request end bitwise equal to their runs alone."""
+    from paper_2310_11186_amd import tsgne as T
+    reqs = synth.serving_requests(48)
+    n_iter = 12
+    params = T.tsgne_params_default(exaggeration_iters=125)
+    srv = T.Server(params=params)
+    tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, n_iter) for gi in reqs]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(st == T.TSGNE_OK for st, _ in outs)
+    order = sorted(range(len(reqs)), key=lambda k: reqs[k].n)
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        gi = reqs[k]
+        R = 8 if gi.n < 131072 else 0
+        import torch
+        rp, col = T.tsgne_csr_from_edges(gi.n, gi.edges)
+        g = T.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                            torch.from_numpy(gi.X).to(gpu), 30.0)
+        Y = torch.from_numpy(gi.Y0).to(gpu)
+        T.tsgne_run(g, Y, n_iter, T.tsgne_params_default(exaggeration_iters=125, tile_rows=R,
+                                                         repulsion=T.TSGNE_REPULSION_SYMMETRIC))
+        assert np.array_equal(Y.cpu().numpy(), outs[k][1]), gi.n
+        g.close()
