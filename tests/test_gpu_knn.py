@@ -29,6 +29,17 @@ def test_knn_graph_bit_exact(gpu, kind, n, k):
     assert np.array_equal(kcol.cpu().numpy(), ocol)
 
 
+def test_knn_graph_full_size(gpu):
+    """The benchmark's construction: the 300,000-node, 1,000,000-edge graph
+    with k = 90 (46M entries), bit-exact against the oracle."""
+    gi = synth.make("dcsbm300k")
+    rp, col, d_rp, d_col = device_csr(gi, gpu)
+    krp, kcol = tsgne.tsgne_knn_graph(d_rp, d_col, 90)
+    orp, ocol = oracle.knn_graph(rp, col, 90)
+    assert np.array_equal(krp.cpu().numpy(), orp)
+    assert np.array_equal(kcol.cpu().numpy(), ocol)
+
+
 def test_affinities_on_knn_graph(gpu):
     gi = synth.small_dcsbm(2500, 7500, 2.4, 12, 8, 21)
     rp, col, d_rp, d_col = device_csr(gi, gpu)

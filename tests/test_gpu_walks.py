@@ -45,6 +45,17 @@ def test_walk_P_bit_exact(gpu, name, make, walks, length, seed):
     g.close()
 
 
+def test_walk_P_full_size(gpu):
+    """The benchmark's construction: 32 walks of 3 steps from every node of the
+    300,000-node, 1,000,000-edge graph, bit-exact against the oracle."""
+    gi = synth.make("dcsbm300k")
+    g, ex, (orp, ocol, oP) = both(gpu, gi.n, gi.edges, gi.X, 32, 3, synth.MASTER_SEED + 9)
+    assert np.array_equal(ex["row_ptr"], orp)
+    assert np.array_equal(ex["col"], ocol)
+    assert np.array_equal(ex["P"], oP)
+    g.close()
+
+
 def test_walk_P_path_and_no_edges(gpu):
     import torch
     n = 200
