@@ -244,6 +244,8 @@ def run_serve(args) -> int:
     log("one at a time: p50 %.0f ms, p99 %.0f ms" % (st1["latency_p50_ms"], st1["latency_p99_ms"]))
     st_eq, wall_eq = serve_stream(dict(kw, oldest_share=0.0), reqs, arrivals, n_iter)
     log("equal shares: p50 %.0f ms, p99 %.0f ms" % (st_eq["latency_p50_ms"], st_eq["latency_p99_ms"]))
+    st_sf, wall_sf = serve_stream(dict(kw, rest_policy=tsgne.TSGNE_SHARE_SMALLEST_FIRST), reqs, arrivals, n_iter)
+    log("smallest first: p50 %.0f ms, p99 %.0f ms" % (st_sf["latency_p50_ms"], st_sf["latency_p99_ms"]))
     load = []
     for frac in [float(v) for v in args.qps_fractions.split(",") if v]:
         if frac == 0.8:
@@ -282,6 +284,7 @@ def run_serve(args) -> int:
                       "speedup_vs_one_at_a_time": wall_sat1 / wall_sat},
         "one_at_a_time": summary(st1, wall1),
         "equal_shares": summary(st_eq, wall_eq),
+        "smallest_first": dict(summary(st_sf, wall_sf), by_size_decile=by_size_decile(reqs, st_sf)),
         "by_size_decile": by_size_decile(reqs, st),
         "by_size_decile_one_at_a_time": by_size_decile(reqs, st1),
         "by_load": load,

@@ -457,9 +457,15 @@ typedef struct tsgne_server_config {
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
   float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
   float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared
-                              equally (default 0.5; 0 = equal shares for all); bounds how far small arrivals can
-                              slow the request that has waited longest */
+                              by rest_policy (default 0.5; 0 = the whole round by rest_policy); bounds how far
+                              small arrivals can slow the request that has waited longest */
+  int32_t rest_policy;     /* how the rest of a round is shared: TSGNE_SHARE_EQUAL (default) in equal parts,
+                              TSGNE_SHARE_SMALLEST_FIRST to the requests with the least remaining work first
+                              (each as many steps as a round allows until the time runs out) */
 } tsgne_server_config;
+
+#define TSGNE_SHARE_EQUAL 0
+#define TSGNE_SHARE_SMALLEST_FIRST 1
 
 typedef struct tsgne_request {
   int32_t n;             /* nodes */

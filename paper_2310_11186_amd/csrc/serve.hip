@@ -321,14 +321,34 @@ void tsgne_server::run() {
     for (size_t k = 1; k < active.size(); ++k)
       if (active[k].req->t_submit < active[oldest].req->t_submit) oldest = k;
     const bool favour = cfg.oldest_share > 0.f && active.size() > 1;
+    auto per_step_of = [&](size_t k) { return (double)active[k].req->n * (double)(active[k].req->n - 1) + 1.0; };
+    // Smallest-first: the time left after the oldest request's part goes to
+    // the requests with the least remaining work, each as much as a round
+    // allows, until it runs out (the others still take one step).
+    std::vector<double> share_of(active.size(), 0.0);
+    if (cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST && budget > 0.0) {
+      std::vector<size_t> rest;
+      for (size_t k = 0; k < active.size(); ++k)
+        if (!(favour && k == oldest)) rest.push_back(k);
+      auto remaining = [&](size_t k) { return per_step_of(k) * (double)(active[k].req->n_iter - active[k].progress); };
+      std::stable_sort(rest.begin(), rest.end(), [&](size_t a, size_t b) { return remaining(a) < remaining(b); });
+      double left = favour ? budget * (1.0 - cfg.oldest_share) : budget;
+      for (size_t k : rest) {
+        const double want = per_step_of(k) * (double)std::min(cfg.steps_per_round, active[k].req->n_iter - active[k].progress);
+        share_of[k] = std::min(want, left);
+        left -= share_of[k];
+      }
+      if (favour) share_of[oldest] = budget * cfg.oldest_share;
+    }
     for (size_t k = 0; k < active.size(); ++k) {
       const Slot& sl = active[k];
-      const double per_step = (double)sl.req->n * (double)(sl.req->n - 1) + 1.0;
-      const double share = !favour ? budget / (double)active.size()
+      const double per_step = per_step_of(k);
+      const double share = cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST ? share_of[k]
+                           : !favour ? budget / (double)active.size()
                            : k == oldest ? budget * cfg.oldest_share
                                          : budget * (1.0 - cfg.oldest_share) / (double)(active.size() - 1);
       int32_t steps = cfg.steps_per_round;
-      if (share > 0.0) steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
+      if (budget > 0.0) steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
       steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
       take[k] = steps;
       lim[k] = sl.progress + steps;
@@ -445,6 +465,7 @@ void tsgne_server_config_default(tsgne_server_config* c) {
   c->steps_per_round = 64;
   c->round_ms = 25.0f;
   c->oldest_share = 0.5f;
+  c->rest_policy = TSGNE_SHARE_EQUAL;
   c->tile_rows = 0;
   tsgne_params_default(&c->params);
 }
@@ -456,6 +477,8 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
   if (!std::isfinite(cfg->round_ms)) return fail(TSGNE_E_INVAL, "round_ms must be finite");
   if (!(cfg->oldest_share >= 0.f && cfg->oldest_share < 1.f))
     return fail(TSGNE_E_INVAL, "oldest_share must lie in [0, 1)");
+  if (cfg->rest_policy != TSGNE_SHARE_EQUAL && cfg->rest_policy != TSGNE_SHARE_SMALLEST_FIRST)
+    return fail(TSGNE_E_INVAL, "rest_policy must be TSGNE_SHARE_EQUAL or TSGNE_SHARE_SMALLEST_FIRST");
   if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
     return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
   if (cfg->tile_rows != 0 && !tile_rows_supported(cfg->tile_rows))

@@ -32,6 +32,9 @@ TSGNE_REPULSION_AUTO = 0
 TSGNE_REPULSION_DIRECT = 1
 TSGNE_REPULSION_SYMMETRIC = 2
 
+TSGNE_SHARE_EQUAL = 0
+TSGNE_SHARE_SMALLEST_FIRST = 1
+
 # every symbol include/tsgne.h declares
 EXPORTED = (
     "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
@@ -83,6 +86,7 @@ class tsgne_server_config(ctypes.Structure):
         ("params", tsgne_params),
         ("round_ms", ctypes.c_float),
         ("oldest_share", ctypes.c_float),
+        ("rest_policy", ctypes.c_int32),
     ]
 
 
@@ -589,7 +593,7 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
                  steps_per_round: int = 64, tile_rows: int = 0, params: tsgne_params | None = None,
-                 round_ms: float = 25.0, oldest_share: float | None = None):
+                 round_ms: float = 25.0, oldest_share: float | None = None, rest_policy: int | None = None):
         cfg = tsgne_server_config()
         lib().tsgne_server_config_default(ctypes.byref(cfg))
         cfg.hbm_budget = int(hbm_budget)
@@ -600,6 +604,8 @@ class Server:
         cfg.round_ms = float(round_ms)
         if oldest_share is not None:
             cfg.oldest_share = float(oldest_share)
+        if rest_policy is not None:
+            cfg.rest_policy = int(rest_policy)
         if params is not None:
             cfg.params = params
         h = ctypes.c_void_p(None)

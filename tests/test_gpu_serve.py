@@ -34,10 +34,14 @@ def requests(seed):
     return gis, iters
 
 
-@pytest.mark.parametrize("max_active,budget_scale,round_ms,oldest", [(3, 0, 25.0, 0.5), (64, 1.3, 25.0, 0.5),
-                                                                     (64, 0, 0.0, 0.5), (64, 0, 0.05, 0.5),
-                                                                     (64, 0, 0.05, 0.0), (64, 0, 0.05, 0.9)])
-def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
+EQ, SF = tsgne.TSGNE_SHARE_EQUAL, tsgne.TSGNE_SHARE_SMALLEST_FIRST
+
+
+@pytest.mark.parametrize("max_active,budget_scale,round_ms,oldest,policy", [
+    (3, 0, 25.0, 0.5, EQ), (64, 1.3, 25.0, 0.5, EQ), (64, 0, 0.0, 0.5, EQ), (64, 0, 0.05, 0.5, EQ),
+    (64, 0, 0.05, 0.0, EQ), (64, 0, 0.05, 0.9, EQ), (64, 0, 0.05, 0.5, SF), (64, 0, 0.05, 0.0, SF),
+    (3, 1.3, 0.05, 0.5, SF)])
+def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, policy):
     gis, iters = requests(1)
     budget = 0
     if budget_scale:
@@ -46,7 +50,8 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest):
         nb = (2100 + 64 * R - 1) // (64 * R)
         budget = int(budget_scale * (8 * nb * nb * 64 * R + 2100 * 400 + 40 * 2100 * 6))
     srv = tsgne.Server(hbm_budget=budget, max_active=max_active, steps_per_round=7, tile_rows=4,
-                       params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms, oldest_share=oldest)
+                       params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms, oldest_share=oldest,
+                       rest_policy=policy)
     tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
     outs = [srv.wait(t) for t in tickets]
     st = srv.stats()
@@ -121,6 +126,10 @@ def test_server_config_rejects(gpu):
     for bad in (1.0, -0.1, float("nan")):
         with pytest.raises(tsgne.TsgneError) as e:
             tsgne.Server(oldest_share=bad)
+        assert e.value.status == tsgne.TSGNE_E_INVAL
+    for bad in (2, -1):
+        with pytest.raises(tsgne.TsgneError) as e:
+            tsgne.Server(rest_policy=bad)
         assert e.value.status == tsgne.TSGNE_E_INVAL
 
 
