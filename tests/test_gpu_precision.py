@@ -3,8 +3,9 @@
 TSGNE_PREC_SPLIT: FP32 pair arithmetic, FP64 for Z, the cross-tile force sums,
 the attraction sums and KL.  TSGNE_PREC_FP32: everything in FP32.  P is
 computed in FP64 and stored in FP32 in both modes.  The measured table is
-written to gpurun_out/precision_report.json when that folder exists; the
-assertions are the bars for the split mode and loose sanity bounds for FP32.
+written to precision_report.json in the folder named by the environment
+variable TSGNE_REPORT_DIR, when it is set and exists; the assertions are the
+bars for the split mode and loose sanity bounds for FP32.
 """
 import json
 import os
@@ -17,7 +18,7 @@ from paper_2310_11186_amd import synth, tsgne
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+OUT = os.environ.get("TSGNE_REPORT_DIR", "")
 
 
 def rel_l2(a, b):
@@ -70,7 +71,7 @@ def test_precision_split_vs_fp32(gpu):
             entry[mode_name] = res
         report[name] = entry
         g.close()
-        if os.path.isdir(OUT):
+        if OUT and os.path.isdir(OUT):
             with open(os.path.join(OUT, "precision_report.json"), "w") as f:
                 json.dump(report, f, indent=1)
         sp, fp = entry["split"], entry["fp32"]
@@ -113,7 +114,7 @@ def test_precision_c3_subsample(gpu):
                        "Z_rel_at_oracle_state": abs(Z.item() / oZ - 1.0),
                        "traj_rel_l2": rel_l2(Yg.cpu().numpy(), oY)}
     g.close()
-    if os.path.isdir(OUT):
+    if OUT and os.path.isdir(OUT):
         path = os.path.join(OUT, "precision_report.json")
         report = json.load(open(path)) if os.path.exists(path) else {}
         report["dcsbm300k_snowball20k"] = entry
