@@ -199,6 +199,12 @@ WORKLOADS = {
                           1000, 250),
     "dcsbm300k": Workload("dcsbm300k", "DC-SBM 300,000 nodes, 1,000,000 edges, gamma 2.3, 200 communities, d=128",
                           1000, 250),
+    # scale points beyond the paper-scale graph, sized like its largest
+    # inputs (about 1.1M nodes / 3M edges and 3M nodes / 4.9M edges)
+    "dcsbm1m": Workload("dcsbm1m", "DC-SBM 1,000,000 nodes, 3,000,000 edges, gamma 2.3, 500 communities, d=128",
+                        1000, 250),
+    "dcsbm3m": Workload("dcsbm3m", "DC-SBM 3,000,000 nodes, 5,000,000 edges, gamma 2.3, 1000 communities, d=64",
+                        1000, 250),
 }
 
 
@@ -219,6 +225,16 @@ def make(name: str, seed: int | None = None) -> GraphInput:
         edges, labels = dcsbm(300_000, 1_000_000, 2.3, 200, 0.18, s)
         X = embedding(labels, 128, 0.5, s)
         return GraphInput(300_000, edges, labels, X, initial_layout(300_000, s), name)
+    if name == "dcsbm1m":
+        s = MASTER_SEED + 21 if seed is None else seed
+        edges, labels = dcsbm(1_000_000, 3_000_000, 2.3, 500, 0.18, s)
+        X = embedding(labels, 128, 0.5, s)
+        return GraphInput(1_000_000, edges, labels, X, initial_layout(1_000_000, s), name)
+    if name == "dcsbm3m":
+        s = MASTER_SEED + 22 if seed is None else seed
+        edges, labels = dcsbm(3_000_000, 5_000_000, 2.3, 1000, 0.18, s)
+        X = embedding(labels, 64, 0.5, s)
+        return GraphInput(3_000_000, edges, labels, X, initial_layout(3_000_000, s), name)
     raise KeyError(name)
 
 
