@@ -115,7 +115,7 @@ def run_batch(args) -> int:
     Y0 = [torch.from_numpy(gi.Y0).to(dev) for gi in gis]
     params = tsgne.tsgne_params_default(exaggeration_iters=t_ee)
     best, ms = tsgne.tsgne_autotune(graphs, Y0, params, steps=3)
-    log("autotuner: ms/step for tile_rows 4, 8, 16 = %s -> %d" % (["%.2f" % m for m in ms], best))
+    log("autotuner: ms/step for tile_rows %s = %s -> %d" % (tsgne.AUTOTUNE_TILES, ["%.2f" % m for m in ms], best))
     params_b = tsgne.tsgne_params_default(exaggeration_iters=t_ee, tile_rows=best)
     pairs = sum(float(gi.n) * (gi.n - 1) for gi in gis) * n_iter
 

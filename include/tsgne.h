@@ -416,12 +416,14 @@ TSGNE_API tsgne_status tsgne_batch_run(tsgne_graph* const* graphs, float* const*
 
 /*
  * Autotuner: times `steps` batched steps (after one warm-up step) of the given
- * graphs for each repulsion tile R in {4, 8, 16}, on scratch copies of Y_d
- * (the caller's layouts are only read), and returns the fastest R in
- * *best_tile_rows and, if ms_per_step is not NULL, the three average step
- * times (ms) in that order.  Leaves the graphs' workspaces planned for R = 16.
- * Synchronising.  Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ * graphs for each repulsion tile R in {4, 8, 12, 16} (TSGNE_AUTOTUNE_TILES
+ * values), on scratch copies of Y_d (the caller's layouts are only read), and
+ * returns the fastest R in *best_tile_rows and, if ms_per_step is not NULL,
+ * the average step times (ms) in that order: ms_per_step must hold
+ * TSGNE_AUTOTUNE_TILES doubles.  Leaves the graphs' workspaces planned for
+ * R = 16.  Synchronising.  Errors: E_INVAL, E_NOMEM, E_DEVICE.
  */
+#define TSGNE_AUTOTUNE_TILES 4
 TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d, int32_t count,
                                       const tsgne_params* p, int32_t steps, int32_t* best_tile_rows,
                                       double* ms_per_step, void* stream);

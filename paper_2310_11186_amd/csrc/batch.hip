@@ -277,7 +277,7 @@ tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d,
   for (int32_t k = 0; k < count; ++k)
     TSGNE_HIP(dalloc(&scratch[(size_t)k], 2 * (size_t)graphs[k]->n), "allocate scratch layout");
   std::vector<int32_t> iters((size_t)count, steps + 1);
-  const int32_t candidates[3] = {4, 8, 16};
+  const int32_t candidates[TSGNE_AUTOTUNE_TILES] = {4, 8, 12, 16};
   double best = INFINITY;
   int32_t best_R = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -290,7 +290,7 @@ tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* const* Y_d,
       (void)hipEventDestroy(b);
     }
   } ev{e0, e1};
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < TSGNE_AUTOTUNE_TILES; ++c) {
     const int32_t R = candidates[c];
     for (int32_t k = 0; k < count; ++k)
       TSGNE_HIP(hipMemcpyAsync(scratch[(size_t)k], Y_d[k], sizeof(float) * 2 * graphs[k]->n,

@@ -32,6 +32,8 @@ TSGNE_REPULSION_AUTO = 0
 TSGNE_REPULSION_DIRECT = 1
 TSGNE_REPULSION_SYMMETRIC = 2
 
+AUTOTUNE_TILES = (4, 8, 12, 16)   # the autotuner's candidates, in its output order
+
 TSGNE_SHARE_EQUAL = 0
 TSGNE_SHARE_SMALLEST_FIRST = 1
 
@@ -576,12 +578,12 @@ def tsgne_batch_run(graphs, Ys, n_iter, params: tsgne_params, stream=None) -> No
 
 
 def tsgne_autotune(graphs, Ys, params: tsgne_params, steps: int = 3, stream=None) -> tuple[int, list]:
-    """(fastest tile_rows, [ms per step for tile_rows 4, 8, 16]) for this batch."""
+    """(fastest tile_rows, [ms per step for tile_rows 4, 8, 12, 16]) for this batch."""
     count = len(graphs)
     hs = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
     ys = (ctypes.c_void_p * count)(*[Y.data_ptr() for Y in Ys])
     best = ctypes.c_int32(0)
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * len(AUTOTUNE_TILES))()
     _check(lib().tsgne_autotune(hs, ys, count, ctypes.byref(params), int(steps), ctypes.byref(best), ms,
                                 _stream(stream)))
     return best.value, list(ms)
