@@ -628,7 +628,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, sbm2k, dcsbm1m, dcsbm3m, batch256, serve, sparse, sp, walks, knn or shard")
+    ap.add_argument("--workload", default="dcsbm300k", help="dcsbm300k, dcsbm100k, dcsbm20k, sbm2k, dcsbm1m, dcsbm3m, dcsbm_n<N> (any size), batch256, serve, sparse, "
+                         "sp, walks, knn or shard")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests in the stream")
     ap.add_argument("--qps-fractions", default="0.5,0.8,0.95", metavar="LIST",
                     help="serve: Poisson arrival rates as fractions of the saturated rate (comma list)")
@@ -685,7 +686,8 @@ def main() -> int:
         return 0
 
     dev = torch.device("cuda:0")
-    wl = synth.WORKLOADS[args.workload]
+    wl = synth.WORKLOADS.get(args.workload) or synth.Workload(
+        args.workload, "DC-SBM of the given size (average degree 8, d = 32)", 1000, 250)
     n_iter = args.n_iter if args.n_iter is not None else wl.n_iter
     t_ee = min(wl.exaggeration_iters, n_iter // 4) if args.n_iter is not None else wl.exaggeration_iters
     log("generating %s" % wl.description)

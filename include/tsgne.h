@@ -82,7 +82,7 @@ typedef struct tsgne_params {
   int32_t precision;          /* TSGNE_PREC_SPLIT (default) or TSGNE_PREC_FP32 */
   int32_t kl_every;           /* tsgne_run: record KL after every kl_every-th step; 0 = off */
   int32_t repulsion;          /* TSGNE_REPULSION_* (default AUTO = SYMMETRIC) */
-  int32_t tile_rows;          /* rows per lane of the repulsion tile: 4, 8, 12, 14, 15, 16 or 0 = auto */
+  int32_t tile_rows;          /* rows per lane of the repulsion tile: 1, 2, 4, 8, 12, 14, 15, 16 or 0 = auto */
 } tsgne_params;
 
 typedef struct tsgne_graph tsgne_graph;
@@ -401,7 +401,7 @@ TSGNE_API tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, 
  * momentum switch at p->exaggeration_iters).  Each step is one set of fused
  * launches for the whole batch (repulsion tiles of every graph, per-graph Z,
  * attraction, update), captured once as a HIP graph and replayed.  All graphs
- * use the repulsion tile p->tile_rows (4, 8, 12, 14, 15, 16; 0 = chosen from the batch's
+ * use the repulsion tile p->tile_rows (1, 2, 4, 8, 12, 14, 15, 16; 0 = chosen from the batch's
  * total tile count) with symmetric tiles; each graph's arithmetic and
  * reduction order are its own, so its result equals tsgne_run of that graph
  * alone with the same tile_rows and the symmetric repulsion, bit for bit.
@@ -455,7 +455,7 @@ typedef struct tsgne_server_config {
   int32_t max_queue;       /* waiting requests before submit returns E_BUSY */
   int32_t steps_per_round; /* most steps a request takes per round (default 64) */
   int32_t tile_rows;       /* repulsion tile rows: 0 (default) = per request (8 below 131072 nodes, the
-                              single-graph plan's choice above); 4, 8, 12, 14, 15 or 16 = for every request */
+                              single-graph plan's choice above); 1, 2, 4, 8, 12, 14, 15 or 16 = for every request */
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
   float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
   float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared
@@ -551,7 +551,7 @@ typedef struct tsgne_shard tsgne_shard;
 
 /*
  * Plans shard `shard` of n_shards for n positions on the current device:
- * tile_rows 4, 8, 12, 14, 15 or 16, or 0 = chosen from the shard's tile
+ * tile_rows 1, 2, 4, 8, 12, 14, 15 or 16, or 0 = chosen from the shard's tile
  * count.  Allocates the tile list, the partial buffer (nb * nb * T float2:
  * 8 bytes per node per block) and the Z partials; *out is library-owned,
  * release it with tsgne_shard_free.  A shard may own no tile (small n, many

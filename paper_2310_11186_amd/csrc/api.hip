@@ -276,7 +276,7 @@ tsgne_status validate_params(const tsgne_params* p) {
   if (p->repulsion < TSGNE_REPULSION_AUTO || p->repulsion > TSGNE_REPULSION_SYMMETRIC)
     return fail(TSGNE_E_INVAL, "unknown repulsion variant");
   if (p->tile_rows != 0 && !tile_rows_supported(p->tile_rows))
-    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 4, 8, 12, 14, 15 or 16");
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 1, 2, 4, 8, 12, 14, 15 or 16");
   return TSGNE_OK;
 }
 

@@ -259,7 +259,7 @@ hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStre
 
 // Rows per lane for which the repulsion kernels are compiled.
 inline bool tile_rows_supported(int32_t R) {
-  return R == 4 || R == 8 || R == 12 || R == 14 || R == 15 || R == 16;
+  return R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15 || R == 16;
 }
 
 // Repulsion plan for n positions (R = 0 picks automatically).

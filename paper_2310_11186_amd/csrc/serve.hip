@@ -482,7 +482,7 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
   if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
     return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
   if (cfg->tile_rows != 0 && !tile_rows_supported(cfg->tile_rows))
-    return fail(TSGNE_E_INVAL, "tile_rows must be 0 (per request), 4, 8, 12, 14, 15 or 16");
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0 (per request), 1, 2, 4, 8, 12, 14, 15 or 16");
   if (cfg->hbm_budget < 0) return fail(TSGNE_E_INVAL, "hbm_budget must be >= 0");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TSGNE_E_DEVICE, "no HIP device");

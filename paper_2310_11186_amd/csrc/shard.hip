@@ -194,7 +194,7 @@ tsgne_status tsgne_shard_create(int32_t n, int32_t shard, int32_t n_shards, int3
   if (n_shards < 1 || n_shards > 65536) return fail(TSGNE_E_INVAL, "n_shards must lie in [1, 65536]");
   if (shard < 0 || shard >= n_shards) return fail(TSGNE_E_INVAL, "shard must lie in [0, n_shards)");
   if (tile_rows != 0 && !tile_rows_supported(tile_rows))
-    return fail(TSGNE_E_INVAL, "tile_rows must be 0 (chosen for the shard), 4, 8, 12, 14, 15 or 16");
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0 (chosen for the shard), 1, 2, 4, 8, 12, 14, 15 or 16");
   const int32_t R = tile_rows ? tile_rows : shard_tile_rows(n, n_shards);
   const int64_t T = (int64_t)kWave * R, nb = (n + T - 1) / T;
   int dev = 0;

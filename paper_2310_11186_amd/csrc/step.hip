@@ -657,6 +657,9 @@ inline unsigned blocks_for(int64_t work, int per) { return (unsigned)((work + pe
 
 // SIMDs of the chip (256 CUs x 4).
 constexpr int64_t kSimds = 1024;
+// Largest graphs that take 1 and 2 rows per lane automatically (see make_plan).
+constexpr int32_t kOneRowMaxNodes = 3500;
+constexpr int32_t kTwoRowMaxNodes = 11000;
 
 RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
   RepulsionPlan p;
@@ -665,6 +668,17 @@ RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
     const int64_t nb = (n + kWave * r - 1) / (kWave * r);
     return p.variant == TSGNE_REPULSION_DIRECT ? nb * nb : nb * (nb + 1) / 2;
   };
+  // Small graphs have too few tiles of 4 or more rows to fill the chip: a
+  // layout step is then set by one tile's latency, and smaller tiles win in
+  // spite of their lower per-pair efficiency.  Crossovers measured on MI355X
+  // over whole layout steps (repulsion, Z sum, update): 1 row per lane up to
+  // about 3,500 nodes (2,000 nodes: 17.7 ms for P and 300 steps against 27.8 ms with
+  // 4 rows), 2 rows up to about 11,000 (5,000 nodes: 24.3 against 31.0 ms),
+  // and from about 11,000 nodes on the cost model below.
+  if (!tile_rows_supported(R) && p.variant == TSGNE_REPULSION_SYMMETRIC) {
+    if (n <= kOneRowMaxNodes) R = 1;
+    else if (n <= kTwoRowMaxNodes) R = 2;
+  }
   if (!tile_rows_supported(R)) {
     // Cost model: the tiles (one wave each) of the busiest SIMD, i.e. the
     // tile count over the chip's 1024 SIMDs rounded up, times the tile area,
@@ -697,6 +711,8 @@ RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
 
 hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s) {
   switch (ws.plan.R) {
+    case 1: return launch_repulsion_r<1>(ws, n, Y, precision, s);
+    case 2: return launch_repulsion_r<2>(ws, n, Y, precision, s);
     case 4: return launch_repulsion_r<4>(ws, n, Y, precision, s);
     case 8: return launch_repulsion_r<8>(ws, n, Y, precision, s);
     case 16: return launch_repulsion_r<16>(ws, n, Y, precision, s);
@@ -776,6 +792,8 @@ hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStre
   hipError_t e = hipSuccess;
   if (bp.n_items > 0) {
     switch (bp.R) {
+      case 1: e = launch_batch_repulse_r<1>(bp, split, s); break;
+      case 2: e = launch_batch_repulse_r<2>(bp, split, s); break;
       case 4: e = launch_batch_repulse_r<4>(bp, split, s); break;
       case 8: e = launch_batch_repulse_r<8>(bp, split, s); break;
       case 16: e = launch_batch_repulse_r<16>(bp, split, s); break;

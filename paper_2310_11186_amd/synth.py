@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import re
 
 import numpy as np
 
@@ -195,6 +196,8 @@ class Workload:
 
 WORKLOADS = {
     "sbm2k": Workload("sbm2k", "SBM 2,000 nodes, 4 x 500, p_in 0.02, p_out 0.0005, d=16", 500, 125),
+    "dcsbm20k": Workload("dcsbm20k", "DC-SBM 20,000 nodes, 80,000 edges, gamma 2.5, 20 communities, d=64",
+                         1000, 250),
     "dcsbm100k": Workload("dcsbm100k", "DC-SBM 100,000 nodes, 400,000 edges, gamma 2.5, 50 communities, d=128",
                           1000, 250),
     "dcsbm300k": Workload("dcsbm300k", "DC-SBM 300,000 nodes, 1,000,000 edges, gamma 2.3, 200 communities, d=128",
@@ -215,6 +218,11 @@ def make(name: str, seed: int | None = None) -> GraphInput:
         edges, labels = sbm([500] * 4, 0.02, 0.0005, s)
         X = embedding(labels, 16, 1.0, s)
         return GraphInput(2000, edges, labels, X, initial_layout(2000, s), name)
+    if name == "dcsbm20k":
+        s = MASTER_SEED + 23 if seed is None else seed
+        edges, labels = dcsbm(20_000, 80_000, 2.5, 20, 0.18, s)
+        X = embedding(labels, 64, 0.5, s)
+        return GraphInput(20_000, edges, labels, X, initial_layout(20_000, s), name)
     if name == "dcsbm100k":
         s = MASTER_SEED + 2 if seed is None else seed
         edges, labels = dcsbm(100_000, 400_000, 2.5, 50, 0.18, s)
@@ -235,6 +243,14 @@ def make(name: str, seed: int | None = None) -> GraphInput:
         edges, labels = dcsbm(3_000_000, 5_000_000, 2.3, 1000, 0.18, s)
         X = embedding(labels, 64, 0.5, s)
         return GraphInput(3_000_000, edges, labels, X, initial_layout(3_000_000, s), name)
+    m = re.fullmatch(r"dcsbm_n(\d+)", name)
+    if m:
+        # a DC-SBM of any size: average degree 8, gamma 2.5, about 1,000 nodes per community, d = 32
+        n = int(m.group(1))
+        s = MASTER_SEED + 24 if seed is None else seed
+        edges, labels = dcsbm(n, 4 * n, 2.5, max(2, n // 1000), 0.18, s)
+        X = embedding(labels, 32, 0.5, s)
+        return GraphInput(n, edges, labels, X, initial_layout(n, s), name)
     raise KeyError(name)
 
 

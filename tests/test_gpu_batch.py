@@ -24,7 +24,7 @@ def small_batch(seed=0):
     return [synth.small_sbm(n, 3, 5.0, 8, seed * 100 + k) for k, n in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("R", [4, 8, 12, 16])
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 12, 16])
 def test_batch_equals_alone_bitwise(gpu, R):
     import torch
     gis = small_batch(1)

@@ -154,6 +154,11 @@ def states(n, seed):
     ("dcsbm", 3001, 12, tsgne.TSGNE_REPULSION_DIRECT),
     ("dcsbm", 3001, 16, tsgne.TSGNE_REPULSION_DIRECT),
     ("dcsbm", 3001, 4, tsgne.TSGNE_REPULSION_DIRECT),
+    ("dcsbm", 3001, 2, tsgne.TSGNE_REPULSION_SYMMETRIC),
+    ("dcsbm", 3001, 1, tsgne.TSGNE_REPULSION_SYMMETRIC),
+    ("sbm", 300, 1, tsgne.TSGNE_REPULSION_SYMMETRIC),
+    ("dcsbm", 3001, 2, tsgne.TSGNE_REPULSION_DIRECT),
+    ("dcsbm", 3001, 1, tsgne.TSGNE_REPULSION_DIRECT),
     ("dcsbm", 3001, 8, tsgne.TSGNE_REPULSION_DIRECT),
     ("sbm2k", 2000, 0, tsgne.TSGNE_REPULSION_AUTO),
 ])

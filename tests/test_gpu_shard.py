@@ -57,7 +57,7 @@ def run_shards(gpu, Y_np, n_shards, R, precision):
     return out
 
 
-@pytest.mark.parametrize("n,n_shards,R", [(1, 1, 4), (2, 3, 8), (700, 2, 4), (1000, 3, 4), (2500, 8, 4),
+@pytest.mark.parametrize("n,n_shards,R", [(1, 1, 4), (2, 3, 8), (700, 2, 4), (1000, 3, 4), (2500, 8, 4), (1000, 4, 1),
                                           (2500, 3, 8), (3001, 2, 15), (3001, 5, 0), (4200, 1, 16)])
 @pytest.mark.parametrize("spread", [0, 8.0])
 def test_shard_against_oracle(gpu, n, n_shards, R, spread):
