@@ -444,8 +444,8 @@ TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* c
  * branches of the round.  Each request's arithmetic depends only on itself
  * and its tile rows: its layout equals tsgne_run of the same graph alone with
  * the symmetric repulsion and tile_rows = the server's tile_rows, or, when
- * that is 0, 8 below 131072 nodes and 0 (the plan's own choice) above, bit
- * for bit.
+ * that is 0, 8 below 131072 nodes and 0 (the plan's own choice) above (0 for
+ * every request when max_active is 1), bit for bit.
  * ------------------------------------------------------------------------ */
 typedef struct tsgne_server tsgne_server;
 
@@ -455,7 +455,8 @@ typedef struct tsgne_server_config {
   int32_t max_queue;       /* waiting requests before submit returns E_BUSY */
   int32_t steps_per_round; /* most steps a request takes per round (default 64) */
   int32_t tile_rows;       /* repulsion tile rows: 0 (default) = per request (8 below 131072 nodes, the
-                              single-graph plan's choice above); 1, 2, 4, 8, 12, 14, 15 or 16 = for every request */
+                              single-graph plan's choice above, and for every request when max_active is 1);
+                              1, 2, 4, 8, 12, 14, 15 or 16 = for every request */
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
   float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
   float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared

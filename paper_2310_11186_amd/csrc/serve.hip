@@ -58,12 +58,12 @@ struct Slot {
 
 // Tile rows of a request when the server does not fix them: graphs with
 // enough tiles to fill the GPU by themselves (kLargeRequest nodes: 128 blocks
-// of 1024) take the single-graph plan's choice, the most efficient per pair;
-// smaller ones take 8, whose short tiles keep their steps short in a shared
-// round.
+// of 1024), and every request of a server that runs one at a time, take the
+// single-graph plan's choice; smaller ones sharing rounds take 8, whose tiles
+// keep a shared round's steps short.
 constexpr int32_t kLargeRequest = 131072;
-int32_t request_tile_rows(int32_t n) {
-  return n >= kLargeRequest ? make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R : 8;
+int32_t request_tile_rows(int32_t n, int32_t max_active) {
+  return (n >= kLargeRequest || max_active == 1) ? make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R : 8;
 }
 
 // Device bytes a request holds while active (graph, workspace, state) plus the
@@ -513,7 +513,7 @@ tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uin
   r->d = rq->d;
   r->n_iter = rq->n_iter;
   r->perplexity = rq->perplexity;
-  r->R = srv->cfg.tile_rows ? srv->cfg.tile_rows : request_tile_rows(rq->n);
+  r->R = srv->cfg.tile_rows ? srv->cfg.tile_rows : request_tile_rows(rq->n, srv->cfg.max_active);
   r->footprint = footprint_bytes(rq->n, rq->m, rq->d, r->R);
   if (r->footprint > (size_t)srv->cfg.hbm_budget)
     return fail(TSGNE_E_NOMEM, "request needs more device memory than the server's budget");

@@ -93,6 +93,19 @@ def test_per_request_tiles_mix_equals_alone(gpu):
         assert np.array_equal(Y, alone(gi, k, 8 if gi.n < 131072 else 0, gpu)), gi.n
 
 
+def test_one_at_a_time_takes_the_single_graph_plan(gpu):
+    # with max_active = 1 and tile_rows = 0 every request is a single-graph
+    # run: its layout equals tsgne_run with the automatic tile
+    gis, iters = requests(3)
+    srv = tsgne.Server(max_active=1, steps_per_round=9, tile_rows=0, params=tsgne.tsgne_params_default(**PARAMS))
+    tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis[:4], iters[:4])]
+    outs = [srv.wait(t) for t in tickets]
+    srv.close()
+    for gi, k, (status, Y) in zip(gis[:4], iters[:4], outs):
+        assert status == tsgne.TSGNE_OK
+        assert np.array_equal(Y, alone(gi, k, 0, gpu)), gi.n
+
+
 def test_failures_stay_with_their_request(gpu):
     gis, iters = requests(2)
     bad = synth.small_sbm(500, 2, 4.0, 8, 77)
