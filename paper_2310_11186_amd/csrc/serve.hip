@@ -38,7 +38,12 @@ struct Request {
   int32_t n = 0, d = 0, n_iter = 0;
   int32_t R = 8;  // repulsion tile rows of this request
   float perplexity = 30.f;
-  std::vector<int32_t> edges;
+  // canonical CSR, built on the submitting thread (prep != OK: the edge list
+  // was refused, and the request fails with that status when admitted)
+  std::vector<int32_t> row_ptr, col;
+  int64_t nnz = 0;
+  tsgne_status prep = TSGNE_OK;
+  std::string prep_error;
   std::vector<float> X, Y0, Y;
   size_t footprint = 0;
   Clock::time_point t_submit, t_admit, t_done;
@@ -120,11 +125,10 @@ void free_slot(Slot& sl) {
 
 // Uploads one request and builds its graph; on failure frees what it made.
 tsgne_status build_slot(const Request& r, int32_t R, hipStream_t s, Slot& out) {
-  std::vector<int32_t> rp((size_t)r.n + 1), col(std::max<size_t>(r.edges.size(), 1));
-  int64_t nnz = 0;
-  if (tsgne_status st = tsgne_csr_from_edges(r.n, (int64_t)r.edges.size() / 2, r.edges.data(), rp.data(),
-                                             col.data(), &nnz))
-    return st;
+  if (r.prep != TSGNE_OK) return fail(r.prep, r.prep_error);
+  const std::vector<int32_t>& rp = r.row_ptr;
+  const std::vector<int32_t>& col = r.col;
+  const int64_t nnz = r.nnz;
   int32_t* d_rp = nullptr;
   int32_t* d_col = nullptr;
   float* d_X = nullptr;
@@ -504,6 +508,7 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
 }
 
 tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uint64_t* ticket) {
+  const Clock::time_point t_call = Clock::now();
   if (!srv || !rq || !ticket) return fail(TSGNE_E_INVAL, "null pointer");
   if (rq->n < 1 || rq->m < 0 || rq->d < 1 || rq->n_iter < 0) return fail(TSGNE_E_INVAL, "bad request sizes");
   if (!std::isfinite(rq->perplexity) || rq->perplexity <= 1.0f) return fail(TSGNE_E_INVAL, "perplexity must be > 1");
@@ -517,13 +522,23 @@ tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uin
   r->footprint = footprint_bytes(rq->n, rq->m, rq->d, r->R);
   if (r->footprint > (size_t)srv->cfg.hbm_budget)
     return fail(TSGNE_E_NOMEM, "request needs more device memory than the server's budget");
-  r->edges.assign(rq->edges_h, rq->edges_h + 2 * rq->m);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if ((int64_t)srv->queue.size() >= srv->cfg.max_queue) return fail(TSGNE_E_BUSY, "request queue is full");
+  }
+  // The canonical CSR is built here, on the caller's thread, so that the
+  // server's worker (which keeps the GPU busy) only uploads and builds P.
+  r->row_ptr.resize((size_t)rq->n + 1);
+  r->col.resize((size_t)std::max<int64_t>(2 * rq->m, 1));
+  r->prep = tsgne_csr_from_edges(rq->n, rq->m, rq->edges_h, r->row_ptr.data(), r->col.data(), &r->nnz);
+  if (r->prep != TSGNE_OK) r->prep_error = tsgne_last_error();
+  r->col.resize((size_t)std::max<int64_t>(r->nnz, 1));
   r->X.assign(rq->X_h, rq->X_h + (size_t)rq->n * rq->d);
   r->Y0.assign(rq->Y0_h, rq->Y0_h + 2 * (size_t)rq->n);
   std::lock_guard<std::mutex> lk(srv->mu);
   if ((int64_t)srv->queue.size() >= srv->cfg.max_queue) return fail(TSGNE_E_BUSY, "request queue is full");
   r->ticket = srv->next_ticket++;
-  r->t_submit = Clock::now();
+  r->t_submit = t_call;
   if (!srv->have_first) {
     srv->have_first = true;
     srv->t_first = r->t_submit;

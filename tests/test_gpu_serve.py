@@ -114,12 +114,16 @@ def test_failures_stay_with_their_request(gpu):
     srv = tsgne.Server(max_active=8, steps_per_round=5, tile_rows=4, params=tsgne.tsgne_params_default(**PARAMS))
     good = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis[:3], iters[:3])]
     tb = srv.submit(bad.n, bad.edges, bad.X, Y0, 30.0, 20)
+    out_of_range = bad.edges.copy()
+    out_of_range[3, 1] = bad.n                 # an endpoint outside [0, n): refused as this request's result
+    tr = srv.submit(bad.n, out_of_range, bad.X, bad.Y0, 30.0, 20)
     long_t = srv.submit(gis[3].n, gis[3].edges, gis[3].X, gis[3].Y0, 30.0, 10 ** 7)
     srv.cancel(long_t)
     status_bad, _ = srv.wait(tb)
     status_long, _ = srv.wait(long_t)
     assert status_bad == tsgne.TSGNE_E_NONFINITE
     assert status_long == tsgne.TSGNE_E_CANCELLED
+    assert srv.wait(tr)[0] == tsgne.TSGNE_E_INVAL
     lat, q = srv.latency(long_t)
     assert 0.0 <= q <= lat
     srv.release(long_t)
@@ -131,7 +135,7 @@ def test_failures_stay_with_their_request(gpu):
         assert status == tsgne.TSGNE_OK
         assert np.array_equal(Y, alone(gi, k, 4, gpu))
     st = srv.stats()
-    assert st["failed"] == 1 and st["cancelled"] == 1 and st["completed"] == 3
+    assert st["failed"] == 2 and st["cancelled"] == 1 and st["completed"] == 3
     srv.close()
 
 
