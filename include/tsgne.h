@@ -497,9 +497,10 @@ TSGNE_API void tsgne_server_config_default(tsgne_server_config* c);
  * Errors: E_INVAL (bad configuration), E_DEVICE, E_NOMEM. */
 TSGNE_API tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** out);
 
-/* Copies the request in and queues it; *ticket identifies it.  Errors: E_INVAL
- * (bad sizes, null buffers), E_NOMEM (its footprint exceeds the whole budget),
- * E_BUSY (queue full).  Graph errors (non-canonical edges are canonicalised;
+/* Copies the request in (making its edge list a canonical CSR on the calling
+ * thread) and queues it; *ticket identifies it.  Errors: E_INVAL (bad sizes,
+ * null buffers), E_NOMEM (its footprint exceeds the whole budget), E_BUSY
+ * (queue full).  Graph errors (non-canonical edges are canonicalised;
  * endpoints out of range) surface as the request's result. */
 TSGNE_API tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* req, uint64_t* ticket);
 
