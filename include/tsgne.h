@@ -90,6 +90,17 @@ typedef struct tsgne_graph tsgne_graph;
 /* Fills *p with the defaults listed above. */
 TSGNE_API void tsgne_params_default(tsgne_params* p);
 
+/*
+ * The repulsion plan a graph of n nodes gets for tile_rows (0 = automatic)
+ * and repulsion (TSGNE_REPULSION_*), without a device: *tile_rows_out the
+ * rows per lane, *tiles_out the tiles per step (the tile triangle for the
+ * symmetric kernel, the whole square for the direct one), *partial_bytes_out
+ * the device bytes of the step's repulsion partials (8 * n * nb).  Any output
+ * may be NULL.  Host only.  Errors: E_INVAL (n < 1, unsupported tile_rows).
+ */
+TSGNE_API tsgne_status tsgne_repulsion_plan(int32_t n, int32_t tile_rows, int32_t repulsion, int32_t* tile_rows_out,
+                                            int64_t* tiles_out, int64_t* partial_bytes_out);
+
 /* Message of the last failure on this thread ("" if none). */
 TSGNE_API const char* tsgne_last_error(void);
 

@@ -383,6 +383,18 @@ using namespace tsgne;
 
 extern "C" {
 
+tsgne_status tsgne_repulsion_plan(int32_t n, int32_t tile_rows, int32_t repulsion, int32_t* tile_rows_out,
+                                  int64_t* tiles_out, int64_t* partial_bytes_out) {
+  if (n < 1) return fail(TSGNE_E_INVAL, "n must be >= 1");
+  if (tile_rows != 0 && !tile_rows_supported(tile_rows))
+    return fail(TSGNE_E_INVAL, "tile_rows must be 0, 1, 2, 4, 8, 12, 14, 15 or 16");
+  const RepulsionPlan pl = make_plan(n, tile_rows, repulsion);
+  if (tile_rows_out) *tile_rows_out = pl.R;
+  if (tiles_out) *tiles_out = pl.items;
+  if (partial_bytes_out) *partial_bytes_out = (int64_t)pl.nb * pl.nb * pl.T * (int64_t)sizeof(float2);
+  return TSGNE_OK;
+}
+
 void tsgne_params_default(tsgne_params* p) {
   if (!p) return;
   p->early_exaggeration = 12.0f;

@@ -39,7 +39,7 @@ TSGNE_SHARE_SMALLEST_FIRST = 1
 
 # every symbol include/tsgne.h declares
 EXPORTED = (
-    "tsgne_params_default", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
+    "tsgne_params_default", "tsgne_repulsion_plan", "tsgne_last_error", "tsgne_status_string", "tsgne_csr_from_edges", "tsgne_knn_graph",
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
     "tsgne_build_P_walks", "tsgne_locality_order", "tsgne_permute_graph", "tsgne_permute_rows",
     "tsgne_graph_from_host_P", "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
@@ -130,6 +130,8 @@ def lib():
         P = ctypes.POINTER(tsgne_params)
         sig = {
             "tsgne_params_default": (None, [P]),
+            "tsgne_repulsion_plan": (st, [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                          ctypes.POINTER(i64)]),
             "tsgne_last_error": (ctypes.c_char_p, []),
             "tsgne_status_string": (ctypes.c_char_p, [st]),
             "tsgne_csr_from_edges": (st, [i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]),
@@ -234,6 +236,14 @@ def tsgne_params_default(**overrides) -> tsgne_params:
             raise AttributeError(k)
         setattr(p, k, v)
     return p
+
+
+def tsgne_repulsion_plan(n: int, tile_rows: int = 0, repulsion: int = TSGNE_REPULSION_AUTO) -> tuple[int, int, int]:
+    """(rows per lane, tiles per step, bytes of repulsion partials) for a graph of n nodes (host only)."""
+    R, tiles, nbytes = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().tsgne_repulsion_plan(int(n), int(tile_rows), int(repulsion), ctypes.byref(R), ctypes.byref(tiles),
+                                      ctypes.byref(nbytes)))
+    return R.value, tiles.value, nbytes.value
 
 
 def tsgne_csr_from_edges(n: int, edges) -> tuple[np.ndarray, np.ndarray]:

@@ -117,3 +117,26 @@ def test_argument_validation_before_device_work():
     assert L.tsgne_shard_timing(None, None, None) == tsgne.TSGNE_E_INVAL
     assert L.tsgne_shard_free(None) == tsgne.TSGNE_OK
     assert L.tsgne_status_string(tsgne.TSGNE_E_GRAPH) == b"TSGNE_E_GRAPH"
+
+
+def test_repulsion_plan_on_the_host():
+    # the automatic tile follows the measured crossovers: 1 row per lane up to
+    # 3,500 nodes, 2 up to 11,000, then the tiles-per-SIMD cost model
+    # (14 rows at the 300K benchmark graph, 15 at 1M and 3M)
+    for n, R in [(1, 1), (2000, 1), (3500, 1), (3501, 2), (11000, 2), (20000, 4), (100000, 8),
+                 (300000, 14), (1000000, 15), (3000000, 15)]:
+        r, tiles, nbytes = tsgne.tsgne_repulsion_plan(n)
+        assert r == R, (n, r)
+        nb = -(-n // (64 * r))
+        assert tiles == nb * (nb + 1) // 2
+        assert nbytes == 8 * nb * nb * 64 * r
+    # a fixed tile and the direct kernel (the whole square of tiles)
+    r, tiles, nbytes = tsgne.tsgne_repulsion_plan(5000, 8, tsgne.TSGNE_REPULSION_DIRECT)
+    assert (r, tiles, nbytes) == (8, 100, 8 * 10 * 10 * 512)
+    # partial buffers as the design states them: about 0.8 GB at 300K, 75 GB at 3M
+    assert abs(tsgne.tsgne_repulsion_plan(300000)[2] / 1e9 - 0.80) < 0.02
+    assert abs(tsgne.tsgne_repulsion_plan(3000000)[2] / 1e9 - 75.0) < 0.5
+    for bad in [(0, 0), (100, 3), (100, 32)]:
+        with pytest.raises(tsgne.TsgneError) as e:
+            tsgne.tsgne_repulsion_plan(*bad)
+        assert e.value.status == tsgne.TSGNE_E_INVAL
