@@ -3,11 +3,12 @@
 // Requests are copied in at submission and queued.  A worker thread owns all
 // device work: between rounds it admits queued requests while their estimated
 // device footprint fits the budget (building their affinities), then advances
-// every active request by `steps_per_round` steps in one captured batched
-// sequence (each request at its own step index), and completes the requests
-// that reached n_iter (layout copied out, memory released).  Requests are
-// grouped by tile size, one batched plan per group, the groups running on
-// parallel branches of each captured round.  Every request's arithmetic and
+// every active request by its share of the round (at most `steps_per_round`
+// steps) in one captured batched sequence (each request at its own step
+// index), and completes the requests that reached n_iter (layout copied out,
+// memory released).  Requests are grouped by tile size, one batched plan per
+// group, the groups running on parallel branches of each captured round, each
+// branch as long as its own group's largest share.  Every request's arithmetic and
 // reduction order depend only on itself and its tile size (a function of its
 // size, or the server's fixed choice), so its layout is the same alone or in
 // any mix.
@@ -256,10 +257,16 @@ void tsgne_server::run() {
   for (int k = 0; k < kMaxGroups && branches_ok; ++k)
     branches_ok = hipStreamCreateWithFlags(&branch[k], hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&join[k], hipEventDisableTiming) == hipSuccess;
-  std::map<int32_t, hipGraphExec_t> execs;  // captured rounds by length, for the current membership
-  auto drop_execs = [&]() {
+  // Captured rounds for the current membership, keyed by the number of steps
+  // each group's branch launches (groups in ascending tile size).
+  std::map<std::vector<int32_t>, hipGraphExec_t> execs;
+  constexpr size_t kMaxExecs = 32;
+  auto clear_execs = [&]() {
     for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
     execs.clear();
+  };
+  auto drop_execs = [&]() {
+    clear_execs();
     plan_valid = false;
   };
   // ordered pairs evaluated per second, refined from measured rounds
@@ -318,7 +325,7 @@ void tsgne_server::run() {
     // With oldest_share > 0 the request that has waited longest gets that
     // fraction of the round and the others split the rest.
     std::vector<int32_t> take(active.size()), lim(active.size());
-    int32_t longest = 1;
+    std::map<int32_t, int32_t> longest;  // per group (tile size): the most steps any member takes
     double pairs = 0.0;
     const double budget = cfg.round_ms > 0.f ? pair_rate * 1e-3 * cfg.round_ms : 0.0;
     size_t oldest = 0;
@@ -356,31 +363,40 @@ void tsgne_server::run() {
       steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
       take[k] = steps;
       lim[k] = sl.progress + steps;
-      longest = std::max(longest, steps);
+      int32_t& most = longest[sl.req->R];
+      most = std::max(most, steps);
       pairs += per_step * steps;
     }
-    int32_t len = 1;
-    while (len < longest) len *= 2;
-    len = std::min(len, cfg.steps_per_round);
+    // Each group's branch launches the power of two at or above its own
+    // longest allotment (members pause at their limit on the device), so a
+    // group of large graphs that take one step in a round does not launch
+    // the many steps a group of small ones takes beside it.
+    std::vector<int32_t> lens;
+    for (const auto& kv : groups) {
+      int32_t len = 1;
+      while (len < longest[kv.first]) len *= 2;
+      lens.push_back(std::min(len, cfg.steps_per_round));
+    }
     if (st == TSGNE_OK) {
       hipError_t e = hipMemcpyAsync(limits, lim.data(), sizeof(int32_t) * lim.size(), hipMemcpyHostToDevice, s);
       if (e != hipSuccess) st = hip_fail(e, "upload round limits");
     }
-    if (st == TSGNE_OK && !execs.count(len)) {
+    if (st == TSGNE_OK && !execs.count(lens)) {
+      if (execs.size() >= kMaxExecs) clear_execs();
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       hipError_t le = hipSuccess;
       if (groups.size() == 1) {
         const BatchRun& br = groups.begin()->second;
-        for (int32_t k = 0; e == hipSuccess && k < len && le == hipSuccess; ++k)
+        for (int32_t k = 0; e == hipSuccess && k < lens[0] && le == hipSuccess; ++k)
           le = launch_batch_step(br.plan(), cfg.params, s);
       } else if (e == hipSuccess) {
         le = hipEventRecord(fork, s);
         int gi = 0;
         for (auto it = groups.begin(); it != groups.end() && le == hipSuccess; ++it, ++gi) {
           le = hipStreamWaitEvent(branch[gi], fork, 0);
-          for (int32_t k = 0; k < len && le == hipSuccess; ++k)
+          for (int32_t k = 0; k < lens[gi] && le == hipSuccess; ++k)
             le = launch_batch_step(it->second.plan(), cfg.params, branch[gi]);
           if (le == hipSuccess) le = hipEventRecord(join[gi], branch[gi]);
         }
@@ -391,10 +407,10 @@ void tsgne_server::run() {
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       if (graph) (void)hipGraphDestroy(graph);
       if (e != hipSuccess) st = hip_fail(e, "capture a serving round");
-      else execs[len] = exec;
+      else execs[lens] = exec;
     }
     if (st == TSGNE_OK) {
-      hipError_t e = hipGraphLaunch(execs[len], s);
+      hipError_t e = hipGraphLaunch(execs[lens], s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = hip_fail(e, "run a serving round");
     }
