@@ -47,6 +47,15 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// The same rotation for a value read once, by the instruction that consumes
+// it.  With a constant "old" operand (never used: every source lane exists)
+// the compiler folds the move into that instruction as its DPP source, so the
+// rotation costs no instruction of its own.
+__device__ __forceinline__ float rotate_lanes_once(float v) {
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, b, 0x13C, 0xF, 0xF, false));
+}
+
 // w = 1 / (1 + dx^2 + dy^2) with the hardware reciprocal (q >= 1, <= 1 ulp).
 __device__ __forceinline__ float student_w(float dx, float dy) {
   return __builtin_amdgcn_rcpf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f)));
@@ -75,15 +84,18 @@ __device__ __forceinline__ void sym_pass(const float (&yix)[R], const float (&yi
       sx = __builtin_fmaf(w2, dx, sx);
       sy = __builtin_fmaf(w2, dy, sy);
     }
-    fx -= sx;
-    fy -= sy;
+    // the column's travelling force trails it by one lane: carried across
+    // and reduced in one instruction
+    fx = rotate_lanes_once(fx) - sx;
+    fy = rotate_lanes_once(fy) - sy;
     if (SPLIT) z64 += (double)zs; else z32 += zs;
     tx = rotate_lanes(tx);
     ty = rotate_lanes(ty);
-    fx = rotate_lanes(fx);
-    fy = rotate_lanes(fy);
     if (MASKED) m = rotate_lanes(m);
   }
+  // after the last step the forces are one lane short of their columns
+  fx = rotate_lanes(fx);
+  fy = rotate_lanes(fy);
 }
 
 template <int R, bool SPLIT>
