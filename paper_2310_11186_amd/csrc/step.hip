@@ -61,37 +61,50 @@ __device__ __forceinline__ float student_w(float dx, float dy) {
   return __builtin_amdgcn_rcpf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, 1.0f)));
 }
 
-// Symmetric tile (a < b).  Block a is always full (a < nb - 1).
-// Accumulation is two-level to keep FP32 chains short: the travelling sum of
-// one step (R terms) is formed apart and then added, and the resident sums are
-// folded into a second FP32 sum after every 64-step pass.
+// One step of a symmetric tile: the R resident rows of this lane against the
+// travelling column now in it.  The step's Z terms go on the chain zs;
+// OPENS starts that chain at the first weight rather than adding it to +0
+// (an add the compiler must keep, as -0 + 0 = +0; no weight is -0).
+template <int R, bool MASKED, bool OPENS>
+__device__ __forceinline__ void sym_step(const float (&yix)[R], const float (&yiy)[R], float (&rix)[R],
+                                         float (&riy)[R], float& tx, float& ty, float& fx, float& fy, float& m,
+                                         float& zs) {
+  float sx = 0.f, sy = 0.f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float dx = yix[r] - tx, dy = yiy[r] - ty;
+    float w = student_w(dx, dy);
+    if (MASKED) w *= m;
+    zs = (OPENS && r == 0) ? w : zs + w;
+    const float w2 = w * w;
+    rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+    riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+    sx = __builtin_fmaf(w2, dx, sx);
+    sy = __builtin_fmaf(w2, dy, sy);
+  }
+  // the column's travelling force trails it by one lane: carried across
+  // and reduced in one instruction
+  fx = rotate_lanes_once(fx) - sx;
+  fy = rotate_lanes_once(fy) - sy;
+  tx = rotate_lanes(tx);
+  ty = rotate_lanes(ty);
+  if (MASKED) m = rotate_lanes(m);
+}
+
+// A 64-step pass of a symmetric tile (a < b; block a is always full,
+// a < nb - 1).  Accumulation is two-level to keep FP32 chains short: the
+// travelling sum of one step (R terms) is formed apart and then added, the
+// resident sums are folded into a second FP32 sum after every pass, and Z is
+// summed in FP32 over two steps (2R terms) before its FP64 sum.
 template <int R, bool SPLIT, bool MASKED>
 __device__ __forceinline__ void sym_pass(const float (&yix)[R], const float (&yiy)[R], float (&rix)[R],
                                          float (&riy)[R], float& tx, float& ty, float& fx, float& fy, float& m,
                                          double& z64, float& z32) {
-#pragma unroll 2
-  for (int s = 0; s < kWave; ++s) {
-    float zs = 0.f, sx = 0.f, sy = 0.f;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float dx = yix[r] - tx, dy = yiy[r] - ty;
-      float w = student_w(dx, dy);
-      if (MASKED) w *= m;
-      zs += w;
-      const float w2 = w * w;
-      rix[r] = __builtin_fmaf(w2, dx, rix[r]);
-      riy[r] = __builtin_fmaf(w2, dy, riy[r]);
-      sx = __builtin_fmaf(w2, dx, sx);
-      sy = __builtin_fmaf(w2, dy, sy);
-    }
-    // the column's travelling force trails it by one lane: carried across
-    // and reduced in one instruction
-    fx = rotate_lanes_once(fx) - sx;
-    fy = rotate_lanes_once(fy) - sy;
+  for (int s = 0; s < kWave; s += 2) {
+    float zs;
+    sym_step<R, MASKED, true>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
+    sym_step<R, MASKED, false>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
     if (SPLIT) z64 += (double)zs; else z32 += zs;
-    tx = rotate_lanes(tx);
-    ty = rotate_lanes(ty);
-    if (MASKED) m = rotate_lanes(m);
   }
   // after the last step the forces are one lane short of their columns
   fx = rotate_lanes(fx);
