@@ -508,21 +508,27 @@ __device__ __forceinline__ void update_row(const float2* __restrict__ part, int3
   const float2* __restrict__ pp = part + (int64_t)k * nb * T + off;
   double rx = 0.0, ry = 0.0;
   float sx = 0.f, sy = 0.f;
-  constexpr int kBatchLoads = 8;  // partials whose loads are issued together
+  // Partials are read in batches of kBatchLoads whose loads are all issued
+  // before the first is added.  The loop body has no branch (a branch around
+  // a load makes the compiler wait for it before the next one is issued), so
+  // past the last block an index is clamped to it: an in-bounds re-read that
+  // adds +0, which leaves a sum started at +0 unchanged.
+  constexpr int kBatchLoads = 32;
   for (int32_t o0 = 0; o0 < nb; o0 += kBatchLoads) {
     float2 v[kBatchLoads];
 #pragma unroll
-    for (int u = 0; u < kBatchLoads; ++u) v[u] = (o0 + u < nb) ? pp[(int64_t)(o0 + u) * T] : make_float2(0.f, 0.f);
+    for (int u = 0; u < kBatchLoads; ++u) v[u] = pp[(int64_t)min(o0 + u, nb - 1) * T];
     // added in block order, exactly as a one-at-a-time loop
+    const int32_t count = nb - o0;
 #pragma unroll
     for (int u = 0; u < kBatchLoads; ++u) {
-      if (o0 + u >= nb) break;
+      const bool in = u < count;
       if (SPLIT) {
-        rx += v[u].x;
-        ry += v[u].y;
+        rx += in ? (double)v[u].x : 0.0;
+        ry += in ? (double)v[u].y : 0.0;
       } else {
-        sx += v[u].x;
-        sy += v[u].y;
+        sx += in ? v[u].x : 0.f;
+        sy += in ? v[u].y : 0.f;
       }
     }
   }
