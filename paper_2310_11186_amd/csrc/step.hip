@@ -434,10 +434,13 @@ __device__ __forceinline__ void attract_row(const int32_t* __restrict__ row_ptr,
     float2 yj[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) yj[u] = Y[j[u]];
-    // entries in increasing order per lane, exactly as a one-at-a-time loop
+    // entries in increasing order per lane, exactly as a one-at-a-time loop.
+    // An entry past the row's end (j = i, p = 0) adds exactly +0, which leaves
+    // a sum started at +0 unchanged; with no branch here the gathers of Y are
+    // all issued before the first is used (a branch would put each behind its
+    // own check and wait).
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (e0 + u * LANES >= e_end) break;
       const float dx = yi.x - yj[u].x, dy = yi.y - yj[u].y;
       const float pw = p[u] * student_w(dx, dy);
       if (SPLIT) {
