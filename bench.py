@@ -45,15 +45,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def repulse_kernel_name(rows: int, split: bool = True, symmetric: bool = True) -> str:
+    """The repulsion kernel instantiation a run launches, as the profiler names it."""
+    return "k_repulse<%d, %s, %s>" % (rows, "true" if split else "false", "true" if symmetric else "false")
+
+
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per repulsion launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and on the same kernel
+    instantiation (tile size, precision, variant) as this run; else None."""
     path = os.path.join(PROFILE_DIR, "repulsion_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
 
@@ -492,7 +498,8 @@ def run_shard(args) -> int:
                    "layout": "N(0, 100 I)", "step": "tsgne_shard_repulsion (tile kernel + Z sum + row sums)"},
         "roofline": {"bound": "alu", "kernel": "k_repulse (shard 0's tiles)", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic("shard_300k"), "flop_per_launch": FLOP_PER_PAIR * pairs0,
+                     "traffic": measured_traffic("shard_300k", repulse_kernel_name(R0)),
+                     "flop_per_launch": FLOP_PER_PAIR * pairs0,
                      "avg_launch_ms": tile0 * 1e3},
         "shards": per_shard,
         "balance_max_over_mean": max(tile_ms) / (sum(tile_ms) / len(tile_ms)),
@@ -774,7 +781,9 @@ def main() -> int:
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS if achieved_tflops else None,
-            "traffic": measured_traffic(args.workload),
+            "traffic": measured_traffic(args.workload, repulse_kernel_name(
+                tsgne.tsgne_repulsion_plan(gi.n, args.tile_rows, rep)[0], prec == tsgne.TSGNE_PREC_SPLIT,
+                rep != tsgne.TSGNE_REPULSION_DIRECT)),
             "flop_per_launch": FLOP_PER_PAIR * pairs_per_iter,
             "avg_launch_ms": avg_rep_s * 1e3,
             "launches": rep_launches,

@@ -140,3 +140,27 @@ def test_repulsion_plan_on_the_host():
         with pytest.raises(tsgne.TsgneError) as e:
             tsgne.tsgne_repulsion_plan(*bad)
         assert e.value.status == tsgne.TSGNE_E_INVAL
+
+
+def test_traffic_is_reported_only_for_the_counted_kernel():
+    """bench.py attaches the committed HBM counter figure only to a run of the
+    kernel instantiation it was counted on (same source, tile size, precision
+    and variant), and that instantiation is the one the default 300K
+    benchmark launches."""
+    import json
+    import os
+
+    import bench
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        "repulsion_dcsbm300k_traffic.json")
+    with open(path) as f:
+        rec = json.load(f)
+    R = tsgne.tsgne_repulsion_plan(300_000, 0, tsgne.TSGNE_REPULSION_AUTO)[0]
+    assert rec["kernel"] == bench.repulse_kernel_name(R)
+    assert bench.measured_traffic("dcsbm300k", bench.repulse_kernel_name(R + 1)) is None
+    assert bench.measured_traffic("dcsbm300k", bench.repulse_kernel_name(R, split=False)) is None
+    assert bench.measured_traffic("dcsbm300k", bench.repulse_kernel_name(R, symmetric=False)) is None
+    if rec["kernel_source_hash"] == bench.kernel_source_hash():
+        assert bench.measured_traffic("dcsbm300k", rec["kernel"]) == rec["bytes_per_launch"]
+    else:
+        assert bench.measured_traffic("dcsbm300k", rec["kernel"]) is None
