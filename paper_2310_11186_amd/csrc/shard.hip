@@ -25,6 +25,11 @@ struct tsgne_shard {
   int32_t n_shards = 1;
   int64_t pairs = 0;  // ordered pairs (i, j), i != j, of this shard's tiles
   Workspace ws;       // plan, tile list, partial buffers (ws.Z unused)
+  // the shard's row blocks in ascending order, and for every row block k the
+  // number of them below k (nb + 1 counts), for the per-row sums
+  int32_t* owned = nullptr;
+  int32_t* below = nullptr;
+  int32_t n_owned = 0;
   // event-pair timing of the tile kernel (tsgne_shard_set_timing)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -40,51 +45,64 @@ __device__ __forceinline__ int32_t block_owner(int32_t a, int32_t nb, int32_t n_
   return min(a, nb - 1 - a) % n_shards;
 }
 
-// F_i = sum over the shard's tiles touching row i of their partial for i.  A
-// workgroup takes 64 rows; its kReduceWaves waves split the blocks o into
+// F_i = sum over the shard's tiles touching row i of their partial for i.
+// The partials of row block k that this shard wrote are those of its own row
+// blocks below k (tiles (o, k)) and, if it owns k, those of every block from k
+// on (tiles (k, o)): a list of blocks in ascending order.  A workgroup takes
+// 64 rows of one row block; its kReduceWaves waves split that list into
 // contiguous quarters, each summing its quarter in block order, and the
 // quarters are added in order (FP64 in split mode, FP32 stored as FP64
-// otherwise), so the result is deterministic.
+// otherwise), so the result is deterministic.  The loads of a batch carry no
+// guard (a guarded load sits behind its own branch and is waited for before
+// the next one is issued): past the quarter's end a list index is clamped to
+// its last entry, an in-bounds re-read that adds +0.  Rows past n read the
+// partial buffer inside their own row block and store nothing.
 constexpr int kReduceWaves = 4;
 
 template <bool SPLIT>
 __global__ __launch_bounds__(kReduceBlock) void k_shard_reduce(const float2* __restrict__ part, int32_t nb, int32_t T,
                                                               int32_t n, int32_t shard, int32_t n_shards,
+                                                              const int32_t* __restrict__ owned,
+                                                              const int32_t* __restrict__ below, int32_t n_owned,
                                                               double2* __restrict__ F) {
   __shared__ double2 acc[kReduceWaves][kWave];
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int32_t i = blockIdx.x * kWave + lane;
-  const bool valid = i < n;
-  const int32_t k = valid ? i / T : 0, off = valid ? i - k * T : 0;
-  const float2* __restrict__ pp = part + (int64_t)k * nb * T + off;
-  const int32_t q = (nb + kReduceWaves - 1) / kReduceWaves;
-  const int32_t o_begin = w * q, o_end = min(nb, o_begin + q);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int32_t row0 = blockIdx.x * kWave;  // T is a multiple of 64: one row block per workgroup
+  const int32_t k = row0 / T;
+  const int32_t i = row0 + lane;
+  const float2* __restrict__ pp = part + (int64_t)k * nb * T + (i - k * T);
+  const int32_t b_k = below[k];
+  const int32_t m = b_k + (block_owner(k, nb, n_shards) == shard ? nb - k : 0);
+  const int32_t q = (m + kReduceWaves - 1) / kReduceWaves;
+  const int32_t t_begin = w * q, t_end = min(m, t_begin + q);
   double rx = 0.0, ry = 0.0;
   float sx = 0.f, sy = 0.f;
-  constexpr int kBatchLoads = 8;  // partials whose loads are issued together
-  for (int32_t o0 = o_begin; valid && o0 < o_end; o0 += kBatchLoads) {
+  constexpr int kBatchLoads = 16;
+  for (int32_t t0 = t_begin; t0 < t_end; t0 += kBatchLoads) {
     float2 v[kBatchLoads];
-    bool own[kBatchLoads];
 #pragma unroll
     for (int u = 0; u < kBatchLoads; ++u) {
-      own[u] = o0 + u < o_end && block_owner(min(k, o0 + u), nb, n_shards) == shard;
-      v[u] = own[u] ? pp[(int64_t)(o0 + u) * T] : make_float2(0.f, 0.f);
+      const int32_t t = min(t0 + u, t_end - 1);
+      const int32_t o = t < b_k ? owned[min(t, n_owned - 1)] : k + (t - b_k);
+      v[u] = pp[(int64_t)o * T];
     }
+    const int32_t count = t_end - t0;
 #pragma unroll
     for (int u = 0; u < kBatchLoads; ++u) {
-      if (!own[u]) continue;
+      const bool in = u < count;
       if (SPLIT) {
-        rx += v[u].x;
-        ry += v[u].y;
+        rx += in ? (double)v[u].x : 0.0;
+        ry += in ? (double)v[u].y : 0.0;
       } else {
-        sx += v[u].x;
-        sy += v[u].y;
+        sx += in ? v[u].x : 0.f;
+        sy += in ? v[u].y : 0.f;
       }
     }
   }
   acc[w][lane] = SPLIT ? make_double2(rx, ry) : make_double2((double)sx, (double)sy);
   __syncthreads();
-  if (w != 0 || !valid) return;
+  if (w != 0 || i >= n) return;
   if (SPLIT) {
     double2 t = acc[0][lane];
     for (int u = 1; u < kReduceWaves; ++u) {
@@ -176,11 +194,13 @@ hipError_t resolve_timing(tsgne_shard* sh) {
   return first;
 }
 
-void free_shard_ws(Workspace& ws) {
-  dfree(ws.items);
-  dfree(ws.part);
-  dfree(ws.zpart);
-  dfree(ws.zpart32);
+void free_shard_buffers(tsgne_shard* sh) {
+  dfree(sh->ws.items);
+  dfree(sh->ws.part);
+  dfree(sh->ws.zpart);
+  dfree(sh->ws.zpart32);
+  dfree(sh->owned);
+  dfree(sh->below);
 }
 
 }  // namespace
@@ -211,16 +231,29 @@ tsgne_status tsgne_shard_create(int32_t n, int32_t shard, int32_t n_shards, int3
   ws.plan.nb = (int32_t)nb;
   ws.plan.variant = TSGNE_REPULSION_SYMMETRIC;
   ws.plan.items = (int64_t)items.size();
+  std::vector<int32_t> owned, below((size_t)nb + 1, 0);
+  for (int32_t a = 0; a < (int32_t)nb; ++a) {
+    below[(size_t)a + 1] = below[(size_t)a];
+    if (owner_host(a, (int32_t)nb, n_shards) == shard) {
+      owned.push_back(a);
+      below[(size_t)a + 1] += 1;
+    }
+  }
+  sh->n_owned = (int32_t)owned.size();
   hipError_t e = hipSuccess;
   if (!items.empty()) {
     e = dalloc(&ws.items, items.size());
     if (e == hipSuccess) e = dalloc(&ws.part, (size_t)(nb * nb * T));
     if (e == hipSuccess) e = dalloc(&ws.zpart, items.size());
     if (e == hipSuccess) e = dalloc(&ws.zpart32, items.size());
+    if (e == hipSuccess) e = dalloc(&sh->owned, owned.size());
+    if (e == hipSuccess) e = dalloc(&sh->below, below.size());
     if (e == hipSuccess) e = hipMemcpy(ws.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sh->owned, owned.data(), owned.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(sh->below, below.data(), below.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
-    free_shard_ws(ws);
+    free_shard_buffers(sh);
     delete sh;
     if (e == hipErrorOutOfMemory)
       return fail(TSGNE_E_NOMEM, "shard workspace (partials of nb * nb tiles) does not fit in device memory");
@@ -279,10 +312,10 @@ tsgne_status tsgne_shard_repulsion(tsgne_shard* sh, const float* Y_d, int32_t pr
   const dim3 grid((unsigned)((sh->n + kWave - 1) / kWave));
   if (split)
     hipLaunchKernelGGL((k_shard_reduce<true>), grid, dim3(kReduceBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, sh->n,
-                       sh->shard, sh->n_shards, reinterpret_cast<double2*>(F_d));
+                       sh->shard, sh->n_shards, sh->owned, sh->below, sh->n_owned, reinterpret_cast<double2*>(F_d));
   else
     hipLaunchKernelGGL((k_shard_reduce<false>), grid, dim3(kReduceBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, sh->n,
-                       sh->shard, sh->n_shards, reinterpret_cast<double2*>(F_d));
+                       sh->shard, sh->n_shards, sh->owned, sh->below, sh->n_owned, reinterpret_cast<double2*>(F_d));
   TSGNE_HIP(hipGetLastError(), "launch shard reduction");
   return TSGNE_OK;
 }
@@ -313,7 +346,7 @@ tsgne_status tsgne_shard_free(tsgne_shard* sh) {
   // buffers may still be in use by queued work
   (void)hipDeviceSynchronize();
   (void)resolve_timing(sh);
-  free_shard_ws(sh->ws);
+  free_shard_buffers(sh);
   delete sh;
   return TSGNE_OK;
 }
