@@ -1,9 +1,10 @@
 """Parity of the HIP path (through the C-ABI) against the FP64 oracle.
 
-Bars: CSR / mirror bit-exact; P within 1e-6 relative L2 (elementwise within
-FP32 rounding above the FP32 normal range); per-step gradient within 1e-5
-relative L2 of FP64 at the same Y; Z within 1e-6 relative and KL within 1e-6
-absolute (FP32 pair weights carry ~1e-7 relative error each).
+Bars (tests/bars.py): CSR / mirror bit-exact; P within 1e-6 relative L2
+(elementwise within FP32 rounding above the FP32 normal range); per-step
+gradient within 1e-5 relative L2 of FP64 at the same Y and, row by row, within
+1e-5 of the sizes of its attractive and repulsive terms; Z within 3e-8
+relative and KL within 1e-7 absolute.
 
 Trajectories.  The optimiser's early phase is chaotic on these graphs: the
 oracle itself, with only its state (P, Y, update, gains) rounded to FP32
@@ -22,20 +23,13 @@ import numpy as np
 import pytest
 
 import oracle
+from bars import GRAD_TOL, KL_TOL, P_TOL, ROW_TOL, Z_TOL, rel_l2, row_error_ratio
 from paper_2310_11186_amd import synth, tsgne
 
 pytestmark = pytest.mark.gpu
 
-GRAD_TOL = 1e-5
 TRAJ_TOL = 1e-4
-P_TOL = 1e-6
 FLT_MIN = float(np.finfo(np.float32).tiny)   # values below are denormal / zero in FP32 storage
-
-
-def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 class Case:
@@ -169,9 +163,12 @@ def test_gradient_and_Z_match_oracle(gpu, kind, n, R, variant):
         for alpha in (1.0, 12.0):
             grad, Z = tsgne.tsgne_gradient(c.graph, c.Y(Y), alpha, p)
             og, oZ = oracle.gradient(c.orp, c.ocol, c.oP, Y.astype(np.float64), alpha)
-            err = rel_l2(grad.cpu().numpy(), og)
+            gg = grad.cpu().numpy()
+            err = rel_l2(gg, og)
             assert err <= GRAD_TOL, (name, alpha, err)
-            assert abs(Z.item() / oZ - 1) <= 1e-6, (name, Z.item(), oZ)
+            worst, row = row_error_ratio(gg, og, Y, oZ)
+            assert worst <= ROW_TOL, (name, alpha, row, worst)
+            assert abs(Z.item() / oZ - 1) <= Z_TOL, (name, Z.item(), oZ)
 
 
 @pytest.mark.parametrize("kind,n", [("dcsbm", 3001), ("sbm2k", 2000)])
@@ -357,8 +354,10 @@ def test_full_run_kl_and_final_gradient(gpu, c1_cases):
     assert abs(kl_gpu - kl_orc) <= 0.02 * kl_orc, (kl_gpu, kl_orc)
     oY32 = f32(oY)
     grad, _ = tsgne.tsgne_gradient(c.graph, c.Y(oY32), 1.0, p)
-    og, _ = oracle.gradient(c.orp, c.ocol, c.oP, oY32, 1.0)
-    assert rel_l2(grad.cpu().numpy(), og) <= GRAD_TOL
+    og, oZ = oracle.gradient(c.orp, c.ocol, c.oP, oY32, 1.0)
+    gg = grad.cpu().numpy()
+    assert rel_l2(gg, og) <= GRAD_TOL
+    assert row_error_ratio(gg, og, oY32, oZ)[0] <= ROW_TOL
 
 
 def test_run_equals_steps_and_is_deterministic(gpu):
@@ -379,7 +378,7 @@ def test_kl_matches_oracle(gpu):
     for name, Y in states(2000, 3).items():
         kl = tsgne.tsgne_kl(c.graph, c.Y(Y))
         okl = oracle.kl(c.orp, c.ocol, c.oP, Y.astype(np.float64))
-        assert abs(kl - okl) <= 1e-6 * max(1.0, abs(okl)), (name, kl, okl)
+        assert abs(kl - okl) <= KL_TOL, (name, kl, okl)
 
 
 def test_run_kl_trace(gpu):

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bars import GRAD_TOL, KL_TOL, P_TOL, ROW_TOL, Z_TOL, rel_l2, row_error_ratio, sample_rows
 from paper_2310_11186_amd import synth, tsgne
 
 pytestmark = pytest.mark.gpu
@@ -21,8 +22,15 @@ pytestmark = pytest.mark.gpu
 OUT = os.environ.get("TSGNE_REPORT_DIR", "")
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+def write_report(key, entry):
+    """Adds one entry to precision_report.json under TSGNE_REPORT_DIR (if set)."""
+    if not (OUT and os.path.isdir(OUT)):
+        return
+    path = os.path.join(OUT, "precision_report.json")
+    report = json.load(open(path)) if os.path.exists(path) else {}
+    report[key] = entry
+    with open(path, "w") as fh:
+        json.dump(report, fh, indent=1)
 
 
 def f32(a):
@@ -71,62 +79,158 @@ def test_precision_split_vs_fp32(gpu):
             entry[mode_name] = res
         report[name] = entry
         g.close()
-        if OUT and os.path.isdir(OUT):
-            with open(os.path.join(OUT, "precision_report.json"), "w") as f:
-                json.dump(report, f, indent=1)
+        write_report(name, entry)
         sp, fp = entry["split"], entry["fp32"]
-        assert entry["P_rel_l2"] <= 1e-6
+        assert entry["P_rel_l2"] <= P_TOL
         for sname in states:
-            assert sp[sname]["grad_rel_l2"] <= 1e-5 and sp[sname]["Z_rel"] <= 1e-6
+            assert sp[sname]["grad_rel_l2"] <= GRAD_TOL and sp[sname]["Z_rel"] <= Z_TOL
             assert fp[sname]["grad_rel_l2"] <= 1e-3 and fp[sname]["Z_rel"] <= 1e-4
         assert sp["traj30_rel_l2"] <= 3 * sp["traj30_fp32_state_oracle_drift"] + 1e-4
-        assert sp["kl_abs"] <= 1e-6
+        assert sp["kl_abs"] <= KL_TOL
     print(json.dumps(report, indent=1))
+
+
+
+
+# States of the 1000-iteration schedule at which the c3 checks compare: the
+# start, the first steps, the end of early exaggeration (t = 250) and its
+# eve, half way, and the end.
+C3_STATES = (0, 1, 10, 125, 250, 500, 1000)
+C3_ITERS, C3_TEE = 1000, 250
+# Bars on the final KL of the 1000-iteration snowball layouts relative to the
+# oracle's (the spread of the oracle's own runs under a 1e-7 perturbation of
+# Y0 is the measure of what rounding alone does to it).
+C3_KL_BAR_SPLIT = 0.05
+C3_KL_BAR_FP32 = 0.08
+
+
+def shadow_step(g, gpu, p, t, s, orp, ocol, oP, eta, early_exaggeration=12.0):
+    """One GPU step from the oracle state s = (Y, U, gains) rounded to FP32,
+    against one oracle step from the same state: (gradient rel L2, worst
+    per-row ratio, update rel L2 outside gain flips, flips)."""
+    import torch
+    Y, U, G = (f32(a) for a in s)
+    alpha, mom = (early_exaggeration, 0.5) if t < C3_TEE else (1.0, 0.8)
+    og, oZ = oracle.gradient(orp, ocol, oP, Y, alpha)
+    oY1, oU1, oG1 = oracle.update(Y, U, G, og, mom, eta)
+    dY, dU, dG = (torch.from_numpy(a.astype(np.float32)).to(gpu) for a in (Y, U, G))
+    gg = torch.empty_like(dY)
+    tsgne.tsgne_step(g, dY, dU, dG, t, p, grad_out=gg)
+    gg = gg.cpu().numpy().astype(np.float64)
+    gU, gG = dU.cpu().numpy().astype(np.float64), dG.cpu().numpy().astype(np.float64)
+    same = np.abs(gG - oG1) <= 1e-6 * np.abs(oG1)   # the gain branch taken alike
+    return (rel_l2(gg, og), row_error_ratio(gg, og, Y, oZ)[0], rel_l2(gU[same], oU1[same]), int((~same).sum()))
 
 
 def test_precision_c3_subsample(gpu):
     """The 300K-node graph's precision check on a 20,000-node BFS snowball
-    sample: 250 steps in the split mode and in all-FP32 against the FP64
-    oracle (KL of the final layouts; gradient and Z at the oracle's final
-    state, where the comparison is free of trajectory chaos)."""
+    sample over the whole schedule: 1000 iterations with early exaggeration
+    for the first 250, the learning rate n / 48, in the split mode and in
+    all-FP32, against the FP64 oracle.
+
+    At each state of C3_STATES on the oracle's trajectory (rounded to FP32)
+    one GPU step is checked against one oracle step (gradient, per-row bound,
+    update vector, Z); the final layouts are compared through KL, whose
+    spread under a 1e-7 perturbation of Y0 sets that bar (the layout itself
+    is a chaotic function of the rounding, reported only)."""
     import torch
     sub = synth.snowball_sample(synth.make("dcsbm300k"), 20_000, seed=1)
-    steps, t_ee = 250, 62
     rp, col = tsgne.tsgne_csr_from_edges(sub.n, sub.edges)
     g = tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
                             torch.from_numpy(sub.X).to(gpu), 30.0)
     oP, _ = oracle.build_P(rp, col, sub.X, 30.0)
     eta = max(sub.n / 48.0, 50.0)
-    oY, _, _, _ = oracle.run(rp, col, oP, sub.Y0, n_steps=steps, exaggeration_iters=t_ee, eta=eta)
+    entry = {"nodes": sub.n, "edges": int(sub.edges.shape[0]), "iterations": C3_ITERS,
+             "exaggeration_iters": C3_TEE, "eta": eta, "P_rel_l2": rel_l2(g.export()["P"], oP)}
+    # the oracle's trajectory, kept at the checked states
+    s = (sub.Y0.astype(np.float64), np.zeros((sub.n, 2)), np.ones((sub.n, 2)))
+    ostates = {0: s}
+    t = 0
+    for t_next in C3_STATES[1:]:
+        Y, U, G, _ = oracle.run(rp, col, oP, *s, t0=t, n_steps=t_next - t, exaggeration_iters=C3_TEE, eta=eta)
+        s, t = (Y, U, G), t_next
+        ostates[t] = s
+        write_report("dcsbm300k_snowball20k_progress", {"oracle_t": t})
+    oY = ostates[C3_ITERS][0]
     o_kl = oracle.kl(rp, col, oP, oY)
-    og, oZ = oracle.gradient(rp, col, oP, oY, 1.0)
-    entry = {"nodes": sub.n, "edges": int(sub.edges.shape[0]), "steps": steps, "oracle_kl": o_kl,
-             "P_rel_l2": rel_l2(g.export()["P"], oP)}
+    entry["oracle_kl"] = o_kl
     for name, mode in (("split", tsgne.TSGNE_PREC_SPLIT), ("fp32", tsgne.TSGNE_PREC_FP32)):
-        p = tsgne.tsgne_params_default(precision=mode, exaggeration_iters=t_ee, learning_rate=eta)
+        p = tsgne.tsgne_params_default(precision=mode, exaggeration_iters=C3_TEE, learning_rate=eta)
+        per_state = {}
+        for t in C3_STATES:
+            Yt = f32(ostates[t][0])
+            alpha = 12.0 if t < C3_TEE else 1.0
+            og, oZ = oracle.gradient(rp, col, oP, Yt, alpha)
+            grad, Z = tsgne.tsgne_gradient(g, torch.from_numpy(Yt.astype(np.float32)).to(gpu), alpha, p)
+            gg = grad.cpu().numpy()
+            st = {"grad_rel_l2": rel_l2(gg, og), "grad_row_ratio": row_error_ratio(gg, og, Yt, oZ)[0],
+                  "Z_rel": abs(Z.item() / oZ - 1.0)}
+            if t < C3_ITERS:
+                st["step_grad_rel_l2"], st["step_row_ratio"], st["step_update_rel_l2"], st["gain_flips"] = \
+                    shadow_step(g, gpu, p, t, ostates[t], rp, col, oP, eta)
+            per_state[str(t)] = st
         Yg = torch.from_numpy(sub.Y0).to(gpu)
-        tsgne.tsgne_run(g, Yg, steps, p)
+        tsgne.tsgne_run(g, Yg, C3_ITERS, p)
         kl = tsgne.tsgne_kl(g, Yg)
-        grad, Z = tsgne.tsgne_gradient(g, torch.from_numpy(oY.astype(np.float32)).to(gpu), 1.0, p)
-        og32, _ = oracle.gradient(rp, col, oP, f32(oY), 1.0)      # the oracle at the same FP32-rounded state
-        entry[name] = {"kl": kl, "kl_rel_to_oracle": kl / o_kl - 1.0,
-                       "grad_rel_l2_at_oracle_state": rel_l2(grad.cpu().numpy(), og32),
-                       "Z_rel_at_oracle_state": abs(Z.item() / oZ - 1.0),
-                       "traj_rel_l2": rel_l2(Yg.cpu().numpy(), oY)}
+        entry[name] = {"states": per_state, "kl": kl, "kl_rel_to_oracle": kl / o_kl - 1.0,
+                       "layout_rel_l2": rel_l2(Yg.cpu().numpy(), oY)}
+        write_report("dcsbm300k_snowball20k", entry)
     g.close()
-    if OUT and os.path.isdir(OUT):
-        path = os.path.join(OUT, "precision_report.json")
-        report = json.load(open(path)) if os.path.exists(path) else {}
-        report["dcsbm300k_snowball20k"] = entry
-        with open(path, "w") as fh:
-            json.dump(report, fh, indent=1)
     print(json.dumps(entry, indent=1))
     sp, fp = entry["split"], entry["fp32"]
-    assert entry["P_rel_l2"] <= 1e-6
-    assert sp["grad_rel_l2_at_oracle_state"] <= 1e-5 and sp["Z_rel_at_oracle_state"] <= 1e-5
-    # After 250 steps the layout is past the chaotic early phase: the FP64
-    # oracle itself, started from Y0 perturbed by 1e-7 relative, ends with KL
-    # between -0.9 % and +3.4 % of its unperturbed run (5 perturbed runs), so
-    # the final KL is held to a bar above that spread, not to rounding error
-    assert abs(sp["kl_rel_to_oracle"]) <= 0.05
-    assert fp["grad_rel_l2_at_oracle_state"] <= 1e-3 and abs(fp["kl_rel_to_oracle"]) <= 0.08
+    assert entry["P_rel_l2"] <= P_TOL
+    for t, st in sp["states"].items():
+        assert st["grad_rel_l2"] <= GRAD_TOL and st["grad_row_ratio"] <= ROW_TOL, (t, st)
+        assert st["Z_rel"] <= Z_TOL, (t, st)
+        if "step_grad_rel_l2" in st:
+            assert st["step_grad_rel_l2"] <= GRAD_TOL and st["step_row_ratio"] <= ROW_TOL, (t, st)
+            assert st["step_update_rel_l2"] <= GRAD_TOL, (t, st)
+            assert st["gain_flips"] <= 1e-3 * 2 * sub.n, (t, st)
+    for t, st in fp["states"].items():
+        assert st["grad_rel_l2"] <= 1e-3 and st["Z_rel"] <= 1e-4, (t, st)
+    assert abs(sp["kl_rel_to_oracle"]) <= C3_KL_BAR_SPLIT
+    assert abs(fp["kl_rel_to_oracle"]) <= C3_KL_BAR_FP32
+
+
+def test_c3_trajectory_states_full_graph(gpu):
+    """The 300K-node graph itself along the GPU's own 1000-iteration layout
+    (default parameters: early exaggeration 12 for 250 iterations, learning
+    rate n / 48, automatic tile, precision split): at every state of
+    C3_STATES the gradient of sampled rows (512 seeded random rows, the first
+    and last rows and the first row of the last block of every tile length),
+    Z over all 9e10 ordered pairs and KL are checked against the FP64 oracle
+    at the same FP32 state."""
+    import torch
+    gi = synth.make("dcsbm300k")
+    rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
+    g = tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                            torch.from_numpy(gi.X).to(gpu), 30.0)
+    oP, _ = oracle.build_P(rp, col, gi.X, 30.0)
+    p = tsgne.tsgne_params_default(exaggeration_iters=C3_TEE)
+    rows = sample_rows(gi.n, 512, 23)
+    Y = torch.from_numpy(gi.Y0).to(gpu)
+    U, G = torch.zeros_like(Y), torch.ones_like(Y)
+    snaps = {}
+    t = 0
+    for t_next in C3_STATES:
+        while t < t_next:
+            tsgne.tsgne_step(g, Y, U, G, t, p)
+            t += 1
+        snaps[t] = Y.cpu().numpy()
+    entry = {}
+    for t in C3_STATES:
+        Yt = snaps[t]
+        alpha = 12.0 if t < C3_TEE else 1.0
+        grad, Z = tsgne.tsgne_gradient(g, torch.from_numpy(Yt).to(gpu), alpha, p)
+        kl = tsgne.tsgne_kl(g, torch.from_numpy(Yt).to(gpu))
+        og, oZ = oracle.gradient_rows(rp, col, oP, Yt.astype(np.float64), rows, alpha)
+        gg = grad.cpu().numpy()[rows]
+        entry[str(t)] = {"grad_rel_l2": rel_l2(gg, og), "grad_row_ratio": row_error_ratio(gg, og, Yt, oZ, rows)[0],
+                         "Z_rel": abs(Z.item() / oZ - 1.0),
+                         "kl_abs": abs(kl - oracle.kl_given_Z(rp, col, oP, Yt.astype(np.float64), oZ))}
+        write_report("dcsbm300k_trajectory_states", entry)
+    g.close()
+    print(json.dumps(entry, indent=1))
+    for t, st in entry.items():
+        assert st["grad_rel_l2"] <= GRAD_TOL and st["grad_row_ratio"] <= ROW_TOL, (t, st)
+        assert st["Z_rel"] <= Z_TOL and st["kl_abs"] <= KL_TOL, (t, st)

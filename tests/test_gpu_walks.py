@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bars import GRAD_TOL, Z_TOL
 from paper_2310_11186_amd import synth, tsgne
 
 pytestmark = pytest.mark.gpu
@@ -78,8 +79,8 @@ def test_walk_P_larger_and_gradient(gpu):
     Y = np.random.default_rng(3).standard_normal((gi.n, 2)).astype(np.float32)
     grad, Z = tsgne.tsgne_gradient(g, torch.from_numpy(Y).to(gpu), 1.0)
     og, oZ = oracle.gradient(orp, ocol, oP.astype(np.float64), Y.astype(np.float64), 1.0)
-    assert np.linalg.norm(grad.cpu().numpy() - og) <= 1e-5 * np.linalg.norm(og)
-    assert abs(Z.item() / oZ - 1) <= 1e-6
+    assert np.linalg.norm(grad.cpu().numpy() - og) <= GRAD_TOL * np.linalg.norm(og)
+    assert abs(Z.item() / oZ - 1) <= Z_TOL
     g.close()
 
 

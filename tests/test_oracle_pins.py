@@ -145,6 +145,30 @@ def test_gradient_invariants():
         np.testing.assert_allclose(g3, grad @ R.T, rtol=1e-9, atol=1e-13)
 
 
+def test_gradient_rows_subset_equals_full_gradient_rows():
+    # The row-subset gradient (the checker of sampled rows on large graphs)
+    # must return, in the listed order, exactly the rows of the full gradient
+    # (itself pinned by finite differences above): same Z, same arithmetic per
+    # row, so bitwise equal.  The rows cover the first, the last and a partial
+    # last block of any tile length, unsorted and with a repeat.
+    n = 3001
+    gi = synth.small_dcsbm(n, 9003, 2.4, 15, 6, 5)
+    row_ptr, col = oracle.csr_from_edges(n, gi.edges)
+    P, _ = oracle.build_P(row_ptr, col, gi.X, 5.0)
+    Y = np.random.default_rng(4).standard_normal((n, 2)) * 2.0
+    rng = np.random.default_rng(9)
+    rows = np.concatenate([[n - 1, 0, 2688, 2999], rng.choice(n, 60, replace=False), [n - 1]]).astype(np.int32)
+    for alpha in (1.0, 12.0):
+        full, Zf = oracle.gradient(row_ptr, col, P, Y, alpha)
+        sub, Zs = oracle.gradient_rows(row_ptr, col, P, Y, rows, alpha)
+        assert sub.shape == (rows.shape[0], 2)
+        assert Zs == Zf
+        np.testing.assert_array_equal(sub, full[rows])
+    # an empty subset still returns the full Z
+    sub, Zs = oracle.gradient_rows(row_ptr, col, P, Y, np.zeros(0, np.int32), 1.0)
+    assert sub.shape == (0, 2) and Zs == Zf
+
+
 def test_two_nodes_are_stationary():
     row_ptr, col = oracle.csr_from_edges(2, np.array([[0, 1]]))
     P, _ = oracle.build_P(row_ptr, col, np.zeros((2, 3), np.float32), 30.0)
