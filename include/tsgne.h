@@ -386,10 +386,19 @@ TSGNE_API tsgne_status tsgne_step(tsgne_graph* g, float* Y_d, float* upd_d, floa
 
 /*
  * n_iter steps t = 0 .. n_iter-1 from the layout in Y_d (float32[n][2], in:
- * Y0, out: final layout), with internal upd (0) and gains (1).  Equals n_iter
- * calls of tsgne_step bit for bit.  If p->kl_every > 0 and kl_trace_h is not
- * NULL, kl_trace_h[k] receives the KL (eq. (5), unexaggerated P) after step
- * (k+1)*kl_every - 1, for k < n_iter / kl_every.  Synchronising.
+ * Y0, out: final layout), with internal upd (0) and gains (1): the loop that
+ * minimises eq. (5).  Equals n_iter calls of tsgne_step bit for bit.  The
+ * steps are captured once as a HIP graph of up to 32 steps (the step index
+ * lives on the device, which switches exaggeration and momentum at
+ * exaggeration_iters) and replayed on `stream`; the host does not touch the
+ * layout between steps.  If p->kl_every > 0 and kl_trace_h is not NULL,
+ * kl_trace_h[k] receives the KL (eq. (5), unexaggerated P) after step
+ * (k+1)*kl_every - 1, for k < n_iter / kl_every: computed inside the next
+ * step with the Z that step sums at that layout (FP32-summed Z when
+ * p->precision is TSGNE_PREC_FP32), and for the last layout as tsgne_kl does.
+ * With phase timing on (tsgne_graph_set_timing) the steps are launched one by
+ * one instead, each launch between its own pair of events; the arithmetic is
+ * the same.  Synchronising.
  * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE (the final layout holds a
  * NaN or infinity).
  */
@@ -398,7 +407,10 @@ TSGNE_API tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, con
 
 /*
  * KL(P || Q) of eq. (5) at layout Y_d (float32[n][2]) with the unexaggerated
- * P, accumulated in FP64.  Q's normaliser Z is recomputed at Y_d.
+ * P, accumulated in FP64.  Q's normaliser Z is recomputed at Y_d by a pass
+ * over the repulsion's tiles that forms only the pair weights (FP32 weights,
+ * FP64 sums; bitwise the Z a split-precision step sums at Y_d), about half
+ * the cost of a force pass.
  * *kl_h receives the value.  Synchronising.
  * Errors: E_INVAL, E_NOMEM, E_DEVICE.
  */

@@ -80,6 +80,7 @@ void free_workspace(Workspace& ws) {
   dfree(ws.attract);
   dfree(ws.klpart);
   dfree(ws.klout);
+  dfree(ws.tstep);
   if (ws.pinned) (void)hipHostFree(ws.pinned);
   ws.pinned = nullptr;
   ws.plan = RepulsionPlan{};
@@ -313,6 +314,7 @@ tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p) {
   if (e == hipSuccess) e = dalloc(&ws.attract, (size_t)g->n);
   if (e == hipSuccess) e = dalloc(&ws.klpart, (size_t)ws.kl_blocks);
   if (e == hipSuccess) e = dalloc(&ws.klout, 1);
+  if (e == hipSuccess) e = dalloc(&ws.tstep, 2);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws.pinned), 64 * sizeof(double), 0);
   if (e == hipSuccess)
     e = hipMemcpy(ws.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
@@ -326,7 +328,11 @@ tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p) {
 namespace {
 
 // Repulsion partials, Z, attraction: everything the gradient needs at Y.
-tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipStream_t s) {
+// Inside a run (tstep set) the Z sum also advances the device step counter,
+// and with a trace the step's input layout is sampled for KL when due (with
+// the Z just summed at it, before the update moves it).
+tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipStream_t s, int32_t* tstep = nullptr,
+                            int32_t kl_every = 0, double* trace = nullptr) {
   const float2* Y2 = reinterpret_cast<const float2*>(Y);
   {
     Timed tm(g, TSGNE_PHASE_REPULSION, s);
@@ -334,7 +340,11 @@ tsgne_status enqueue_forces(tsgne_graph* g, const float* Y, int precision, hipSt
   }
   {
     Timed tm(g, TSGNE_PHASE_ZSUM, s);
-    TSGNE_HIP(launch_zsum(g->ws, precision, s), "launch Z reduction");
+    TSGNE_HIP(launch_zsum(g->ws, precision, s, tstep), "launch Z reduction");
+  }
+  if (trace) {
+    Timed tm(g, TSGNE_PHASE_KL, s);
+    TSGNE_HIP(launch_kl(g, Y2, s, tstep, kl_every, trace), "launch KL sample");
   }
   {
     Timed tm(g, TSGNE_PHASE_ATTRACT, s);
@@ -363,16 +373,123 @@ tsgne_status step_impl(tsgne_graph* g, float* Y, float* U, float* G, int32_t t, 
   return TSGNE_OK;
 }
 
+// KL at Y (eq. (5), unexaggerated P): Z from a pass over the repulsion's tiles
+// that forms only the weights (in the split precision, bitwise the Z a step at
+// Y sums), then the FP64 sum over the stored entries.  trace (nullable)
+// receives the value on the device as well.
+tsgne_status enqueue_kl(tsgne_graph* g, const float* Y, hipStream_t s, double* trace = nullptr) {
+  const float2* Y2 = reinterpret_cast<const float2*>(Y);
+  Timed tm(g, TSGNE_PHASE_KL, s);
+  TSGNE_HIP(launch_zonly(g->ws, g->n, Y2, TSGNE_PREC_SPLIT, s), "launch Z pass");
+  TSGNE_HIP(launch_zsum(g->ws, TSGNE_PREC_SPLIT, s), "launch Z reduction");
+  TSGNE_HIP(launch_kl(g, Y2, s, nullptr, 0, trace), "launch KL");
+  return TSGNE_OK;
+}
+
 tsgne_status kl_impl(tsgne_graph* g, const float* Y, double* kl_h, hipStream_t s) {
-  tsgne_status st = enqueue_forces(g, Y, TSGNE_PREC_SPLIT, s);
-  if (st != TSGNE_OK) return st;
-  {
-    Timed tm(g, TSGNE_PHASE_KL, s);
-    TSGNE_HIP(launch_kl(g, reinterpret_cast<const float2*>(Y), s), "launch KL");
-  }
+  if (tsgne_status st = enqueue_kl(g, Y, s)) return st;
   TSGNE_HIP(hipMemcpyAsync(g->ws.pinned, g->ws.klout, sizeof(double), hipMemcpyDeviceToHost, s), "copy KL");
   TSGNE_HIP(hipStreamSynchronize(s), "synchronise KL");
   *kl_h = g->ws.pinned[0];
+  return TSGNE_OK;
+}
+
+// Steps per captured HIP graph of a run (when sampling KL, the smallest
+// multiple of kl_every at or above it, so that every replay samples at the
+// same positions).
+constexpr int32_t kRunChunk = 32;
+
+// One step of a run on the device step counter: alpha and the momentum are
+// read on the device, so the same launches serve every step.
+tsgne_status enqueue_run_step(tsgne_graph* g, float* Y, float* U, float* G, const tsgne_params* p, float eta,
+                              double* trace, hipStream_t s) {
+  int32_t* tstep = g->ws.tstep;
+  if (tsgne_status st = enqueue_forces(g, Y, p->precision, s, tstep, p->kl_every, trace)) return st;
+  StepSchedule sched;
+  sched.tstep = tstep;
+  sched.exaggeration_iters = p->exaggeration_iters;
+  sched.early_exaggeration = p->early_exaggeration;
+  sched.momentum_early = p->momentum_early;
+  sched.momentum_late = p->momentum_late;
+  Timed tm(g, TSGNE_PHASE_UPDATE, s);
+  TSGNE_HIP(launch_update(g, reinterpret_cast<float2*>(Y), reinterpret_cast<float2*>(U), reinterpret_cast<float2*>(G),
+                          1.0f, 0.0f, eta, p->min_gain, p->precision, true, nullptr, nullptr, s, sched),
+            "launch update");
+  return TSGNE_OK;
+}
+
+tsgne_status run_impl(tsgne_graph* g, float* Y, int32_t n_iter, const tsgne_params* p, double* kl_trace_h,
+                      hipStream_t s) {
+  const int32_t n_samples = (kl_trace_h && p->kl_every > 0) ? n_iter / p->kl_every : 0;
+  const size_t len = 2 * (size_t)g->n;
+  ScratchBlock sb_state, sb_misc;
+  sb_state.s = sb_misc.s = s;
+  TSGNE_HIP(scratch_alloc(&sb_state.p, 2 * len * sizeof(float), s), "allocate optimiser state");
+  TSGNE_HIP(scratch_alloc(&sb_misc.p, 256 + sizeof(double) * (size_t)std::max(n_samples, 1), s), "allocate run scratch");
+  float* U = static_cast<float*>(sb_state.p);
+  float* G = U + len;
+  uint32_t* flag = static_cast<uint32_t*>(sb_misc.p);
+  double* trace = n_samples > 0 ? reinterpret_cast<double*>(static_cast<char*>(sb_misc.p) + 256) : nullptr;
+  {
+    std::vector<float> ones(len, 1.0f);
+    TSGNE_HIP(hipMemsetAsync(U, 0, len * sizeof(float), s), "clear update buffer");
+    TSGNE_HIP(hipMemcpyAsync(G, ones.data(), len * sizeof(float), hipMemcpyHostToDevice, s), "set gains");
+    TSGNE_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s), "clear flag");
+    TSGNE_HIP(hipMemsetAsync(g->ws.tstep, 0, 2 * sizeof(int32_t), s), "reset step counter");
+    TSGNE_HIP(hipStreamSynchronize(s), "synchronise run set-up");
+  }
+  const float eta = effective_eta(g, p);
+  int32_t chunk = kRunChunk;
+  if (trace) chunk = (std::max(kRunChunk, p->kl_every) + p->kl_every - 1) / p->kl_every * p->kl_every;
+  // With phase timing on, every launch is bracketed by its own pair of events
+  // on s, so the steps are launched one by one (HIP events recorded during
+  // stream capture order the graph's nodes but cannot be timed).
+  const int32_t replays = g->timer.enabled ? 0 : n_iter / chunk;
+  int32_t done = 0;
+  if (replays > 0) {
+    // Capture on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is launched on s.
+    hipStream_t cs = nullptr;
+    TSGNE_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "create capture stream");
+    struct CS {
+      hipStream_t s;
+      ~CS() { (void)hipStreamDestroy(s); }
+    } cs_guard{cs};
+    TSGNE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    tsgne_status st = TSGNE_OK;
+    for (int32_t k = 0; k < chunk && st == TSGNE_OK; ++k)
+      st = enqueue_run_step(g, Y, U, G, p, eta, (trace && k % p->kl_every == 0) ? trace : nullptr, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    struct GG {
+      hipGraph_t g;
+      hipGraphExec_t x = nullptr;
+      ~GG() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+      }
+    } gg{graph};
+    if (st != TSGNE_OK) return st;
+    TSGNE_HIP(ce, "end capture");
+    TSGNE_HIP(hipGraphInstantiate(&gg.x, graph, nullptr, nullptr, 0), "instantiate run graph");
+    for (int32_t r = 0; r < replays; ++r) TSGNE_HIP(hipGraphLaunch(gg.x, s), "launch run graph");
+    done = replays * chunk;
+  }
+  for (int32_t t = done; t < n_iter; ++t) {
+    const bool sample = trace && (t - done) % p->kl_every == 0;
+    if (tsgne_status st = enqueue_run_step(g, Y, U, G, p, eta, sample ? trace : nullptr, s)) return st;
+  }
+  // the layout after the last step: no step follows to sum Z at it
+  if (n_samples > 0 && n_iter % p->kl_every == 0)
+    if (tsgne_status st = enqueue_kl(g, Y, s, trace + (n_samples - 1))) return st;
+  TSGNE_HIP(launch_nonfinite_check(reinterpret_cast<const float2*>(Y), g->n, flag, s), "launch finiteness check");
+  uint32_t host_flag = 0;
+  TSGNE_HIP(hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read flag");
+  if (n_samples > 0)
+    TSGNE_HIP(hipMemcpyAsync(kl_trace_h, trace, sizeof(double) * (size_t)n_samples, hipMemcpyDeviceToHost, s),
+              "read KL trace");
+  TSGNE_HIP(hipStreamSynchronize(s), "synchronise run");
+  if (host_flag) return fail(TSGNE_E_NONFINITE, "layout holds a NaN or infinity");
   return TSGNE_OK;
 }
 
@@ -637,45 +754,7 @@ tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, const tsgne_p
   if (tsgne_status st = validate_params(p)) return st;
   DeviceGuard dg(g->device);
   if (tsgne_status st = ensure_workspace(g, p)) return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  float *U = nullptr, *G = nullptr;
-  uint32_t* flag = nullptr;
-  struct Bufs {
-    float*& U;
-    float*& G;
-    uint32_t*& flag;
-    ~Bufs() {
-      dfree(U);
-      dfree(G);
-      dfree(flag);
-    }
-  } bufs{U, G, flag};
-  const size_t len = 2 * (size_t)g->n;
-  TSGNE_HIP(dalloc(&U, len), "allocate update buffer");
-  TSGNE_HIP(dalloc(&G, len), "allocate gains");
-  TSGNE_HIP(dalloc(&flag, 1), "allocate flag");
-  {
-    std::vector<float> ones(len, 1.0f);
-    TSGNE_HIP(hipMemsetAsync(U, 0, len * sizeof(float), s), "clear update buffer");
-    TSGNE_HIP(hipMemcpyAsync(G, ones.data(), len * sizeof(float), hipMemcpyHostToDevice, s), "set gains");
-    TSGNE_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s), "clear flag");
-    TSGNE_HIP(hipStreamSynchronize(s), "synchronise run set-up");
-  }
-  int32_t k = 0;
-  for (int32_t t = 0; t < n_iter; ++t) {
-    if (tsgne_status st = step_impl(g, Y_d, U, G, t, p, nullptr, nullptr, s)) return st;
-    if (kl_trace_h && p->kl_every > 0 && (t + 1) % p->kl_every == 0) {
-      double kl = 0.0;
-      if (tsgne_status st = kl_impl(g, Y_d, &kl, s)) return st;
-      kl_trace_h[k++] = kl;
-    }
-  }
-  TSGNE_HIP(launch_nonfinite_check(reinterpret_cast<const float2*>(Y_d), g->n, flag, s), "launch finiteness check");
-  uint32_t host_flag = 0;
-  TSGNE_HIP(hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read flag");
-  TSGNE_HIP(hipStreamSynchronize(s), "synchronise run");
-  if (host_flag) return fail(TSGNE_E_NONFINITE, "layout holds a NaN or infinity");
-  return TSGNE_OK;
+  return run_impl(g, Y_d, n_iter, p, kl_trace_h, reinterpret_cast<hipStream_t>(stream));
 }
 
 tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, void* stream) {

@@ -50,8 +50,19 @@ struct Workspace {
   double2* attract = nullptr;   // [n] sum_j P_ij w_ij (y_i - y_j) (unscaled by alpha)
   double* klpart = nullptr;     // [kl_blocks] KL partial sums
   double* klout = nullptr;      // [1]
+  int32_t* tstep = nullptr;     // [2] device step counter of a run: next step, step being run
   double* pinned = nullptr;     // host-pinned scratch for read-backs
   int32_t kl_blocks = 0;
+};
+
+// The early-exaggeration schedule read on the device by a replayed step
+// (tstep == nullptr: the host passes alpha and the momentum instead).
+struct StepSchedule {
+  const int32_t* tstep = nullptr;
+  int32_t exaggeration_iters = 0;
+  float early_exaggeration = 1.f;
+  float momentum_early = 0.f;
+  float momentum_late = 0.f;
 };
 
 // Per-graph view used by the batched kernels (device memory, one per graph).
@@ -248,12 +259,20 @@ hipError_t launch_symmetrise(const int32_t* mirror, int64_t nnz, const double* p
                              hipStream_t s);
 
 hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s);
-hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s);
+// Z partials only (the repulsion's tiles without forces): bitwise the Z the
+// force pass gives at the same Y and plan; partial forces untouched.
+hipError_t launch_zonly(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s);
+// tstep (nullable): advance a run's device step counter (see Workspace::tstep).
+hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s, int32_t* tstep = nullptr);
 hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, double2* out, hipStream_t s);
 hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gains, float alpha, float momentum,
                          float eta, float min_gain, int precision, bool do_update, float2* grad_out, double* Z_out,
-                         hipStream_t s);
-hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s);
+                         hipStream_t s, const StepSchedule& sched = StepSchedule{});
+// KL at Y with the Z in the workspace into klout; inside a run (tstep set)
+// only on sampled steps, also into trace (see k_kl_final); with tstep null and
+// trace set, also into trace[0].
+hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s, const int32_t* tstep = nullptr,
+                     int32_t kl_every = 0, double* trace = nullptr);
 hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStream_t s);
 

@@ -11,7 +11,8 @@
 // striped over the lanes' registers (membership is one ballot), so nothing is
 // shared through memory inside a wave.  The directed lists are then made
 // symmetric and canonical with a radix sort and a unique pass.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include <algorithm>
 #include <climits>
@@ -241,11 +242,11 @@ tsgne_status tsgne_knn_graph(int32_t n, int64_t nnz, const int32_t* row_ptr_d, c
   // keys below 2^(32 + bits(n)) except the sentinel; sort all 64 bits
   size_t sort_bytes = 0, uniq_bytes = 0;
   const int n_keys = (int)(2 * slots);
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, keys, sorted, n_keys, 0, 64, s), "size sort");
-  TSGNE_HIP(hipcub::DeviceSelect::Unique(nullptr, uniq_bytes, sorted, keys, n_unique, n_keys, s), "size unique");
+  TSGNE_HIP(rocprim::radix_sort_keys(nullptr, sort_bytes, keys, sorted, n_keys, 0, 64, s), "size sort");
+  TSGNE_HIP(rocprim::unique(nullptr, uniq_bytes, sorted, keys, n_unique, (size_t)n_keys, rocprim::equal_to<uint64_t>(), s), "size unique");
   TSGNE_HIP(hipMalloc(&temp, std::max<size_t>(std::max(sort_bytes, uniq_bytes), 1)), "allocate sort scratch");
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(temp, sort_bytes, keys, sorted, n_keys, 0, 64, s), "sort keys");
-  TSGNE_HIP(hipcub::DeviceSelect::Unique(temp, uniq_bytes, sorted, keys, n_unique, n_keys, s), "unique keys");
+  TSGNE_HIP(rocprim::radix_sort_keys(temp, sort_bytes, keys, sorted, n_keys, 0, 64, s), "sort keys");
+  TSGNE_HIP(rocprim::unique(temp, uniq_bytes, sorted, keys, n_unique, (size_t)n_keys, rocprim::equal_to<uint64_t>(), s), "unique keys");
   int64_t host_unique = 0;
   TSGNE_HIP(hipMemcpyAsync(&host_unique, n_unique, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read count");
   TSGNE_HIP(hipStreamSynchronize(s), "synchronise unique");

@@ -7,7 +7,7 @@
 // attraction then stay within a small window of Y.
 // tsgne_permute_graph / tsgne_permute_rows apply such an order to a CSR and
 // to row-major node arrays (and map results back).
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -187,8 +187,8 @@ tsgne_status tsgne_locality_order(int32_t n, const float* X_d, int32_t d, int32_
   const int b = 64 / m;
   const unsigned blocks = blocks_for(n);
   size_t sort_bytes = 0;
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                               (int32_t*)nullptr, (int32_t*)nullptr, n, 0, 64, s),
+  TSGNE_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                     (int32_t*)nullptr, (int32_t*)nullptr, n, 0, 64, s),
             "size sort");
   size_t o = 0;
   const size_t o_err = o;
@@ -223,7 +223,7 @@ tsgne_status tsgne_locality_order(int32_t n, const float* X_d, int32_t d, int32_
   TSGNE_HIP(hipGetLastError(), "launch keys");
   size_t bytes = sort_bytes;
   // ids enter in ascending order and the sort is stable: ties stay by id
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortPairs(base + o_tmp, bytes, key, key2, id, perm_d, n, 0, 64, s),
+  TSGNE_HIP(rocprim::radix_sort_pairs(base + o_tmp, bytes, key, key2, id, perm_d, n, 0, 64, s),
             "sort keys");
   uint32_t host_err = 0;
   TSGNE_HIP(hipMemcpyAsync(&host_err, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read error word");
@@ -241,8 +241,8 @@ tsgne_status tsgne_permute_graph(int32_t n, int64_t nnz, const int32_t* row_ptr_
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int end_bit = bits_for((uint64_t)n * n);
   size_t sort_bytes = 0;
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                              (int)std::max<int64_t>(nnz, 1), 0, end_bit, s),
+  TSGNE_HIP(rocprim::radix_sort_keys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                    (int)std::max<int64_t>(nnz, 1), 0, end_bit, s),
             "size sort");
   size_t o = 0;
   const size_t o_chk = o;
@@ -279,7 +279,7 @@ tsgne_status tsgne_permute_graph(int32_t n, int64_t nnz, const int32_t* row_ptr_
   if (nnz > 0) {
     hipLaunchKernelGGL(k_relabel_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, row_ptr_d, col_d, n, inv, key);
     size_t bytes = sort_bytes;
-    TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(base + o_tmp, bytes, key, key2, (int)nnz, 0, end_bit, s),
+    TSGNE_HIP(rocprim::radix_sort_keys(base + o_tmp, bytes, key, key2, (int)nnz, 0, end_bit, s),
               "sort entries");
   }
   hipLaunchKernelGGL(k_keys_csr, dim3(blocks_for(std::max<int64_t>(nnz, (int64_t)n + 1))), dim3(kBlock), 0, s, key2,

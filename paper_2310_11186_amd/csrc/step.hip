@@ -65,7 +65,9 @@ __device__ __forceinline__ float student_w(float dx, float dy) {
 // travelling column now in it.  The step's Z terms go on the chain zs;
 // OPENS starts that chain at the first weight rather than adding it to +0
 // (an add the compiler must keep, as -0 + 0 = +0; no weight is -0).
-template <int R, bool MASKED, bool OPENS>
+// FORCES = false keeps only the Z terms (the same weights, added in the same
+// order, so Z is bitwise the one the force pass gives).
+template <int R, bool MASKED, bool OPENS, bool FORCES = true>
 __device__ __forceinline__ void sym_step(const float (&yix)[R], const float (&yiy)[R], float (&rix)[R],
                                          float (&riy)[R], float& tx, float& ty, float& fx, float& fy, float& m,
                                          float& zs) {
@@ -76,16 +78,20 @@ __device__ __forceinline__ void sym_step(const float (&yix)[R], const float (&yi
     float w = student_w(dx, dy);
     if (MASKED) w *= m;
     zs = (OPENS && r == 0) ? w : zs + w;
-    const float w2 = w * w;
-    rix[r] = __builtin_fmaf(w2, dx, rix[r]);
-    riy[r] = __builtin_fmaf(w2, dy, riy[r]);
-    sx = __builtin_fmaf(w2, dx, sx);
-    sy = __builtin_fmaf(w2, dy, sy);
+    if (FORCES) {
+      const float w2 = w * w;
+      rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+      riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+      sx = __builtin_fmaf(w2, dx, sx);
+      sy = __builtin_fmaf(w2, dy, sy);
+    }
   }
   // the column's travelling force trails it by one lane: carried across
   // and reduced in one instruction
-  fx = rotate_lanes_once(fx) - sx;
-  fy = rotate_lanes_once(fy) - sy;
+  if (FORCES) {
+    fx = rotate_lanes_once(fx) - sx;
+    fy = rotate_lanes_once(fy) - sy;
+  }
   tx = rotate_lanes(tx);
   ty = rotate_lanes(ty);
   if (MASKED) m = rotate_lanes(m);
@@ -96,22 +102,24 @@ __device__ __forceinline__ void sym_step(const float (&yix)[R], const float (&yi
 // travelling sum of one step (R terms) is formed apart and then added, the
 // resident sums are folded into a second FP32 sum after every pass, and Z is
 // summed in FP32 over two steps (2R terms) before its FP64 sum.
-template <int R, bool SPLIT, bool MASKED>
+template <int R, bool SPLIT, bool MASKED, bool FORCES = true>
 __device__ __forceinline__ void sym_pass(const float (&yix)[R], const float (&yiy)[R], float (&rix)[R],
                                          float (&riy)[R], float& tx, float& ty, float& fx, float& fy, float& m,
                                          double& z64, float& z32) {
   for (int s = 0; s < kWave; s += 2) {
     float zs;
-    sym_step<R, MASKED, true>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
-    sym_step<R, MASKED, false>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
+    sym_step<R, MASKED, true, FORCES>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
+    sym_step<R, MASKED, false, FORCES>(yix, yiy, rix, riy, tx, ty, fx, fy, m, zs);
     if (SPLIT) z64 += (double)zs; else z32 += zs;
   }
   // after the last step the forces are one lane short of their columns
-  fx = rotate_lanes(fx);
-  fy = rotate_lanes(fy);
+  if (FORCES) {
+    fx = rotate_lanes(fx);
+    fy = rotate_lanes(fy);
+  }
 }
 
-template <int R, bool SPLIT>
+template <int R, bool SPLIT, bool FORCES = true>
 __device__ __forceinline__ void tile_symmetric(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                                float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                int64_t item, int lane) {
@@ -136,19 +144,23 @@ __device__ __forceinline__ void tile_symmetric(const float2* __restrict__ Y, int
     // partially valid sub-block (last block only): the mask travels with its position
     float m = vj ? 1.f : 0.f;
     if (q * kWave + kWave <= valid_b)
-      sym_pass<R, SPLIT, false>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
+      sym_pass<R, SPLIT, false, FORCES>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
     else
-      sym_pass<R, SPLIT, true>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
+      sym_pass<R, SPLIT, true, FORCES>(yix, yiy, rix, riy, tx, ty, fx, fy, m, z64, z32);
+    if (FORCES) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      hix[r] += rix[r];
-      hiy[r] += riy[r];
-      rix[r] = riy[r] = 0.f;
+      for (int r = 0; r < R; ++r) {
+        hix[r] += rix[r];
+        hiy[r] += riy[r];
+        rix[r] = riy[r] = 0.f;
+      }
+      if (vj) part[((int64_t)b * nb + a) * T + jl] = make_float2(fx, fy);
     }
-    if (vj) part[((int64_t)b * nb + a) * T + jl] = make_float2(fx, fy);
   }
+  if (FORCES) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+    for (int r = 0; r < R; ++r) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+  }
   // every unordered pair stands for the two ordered pairs of Z
   if (SPLIT) {
     const double z = wave_sum(z64);
@@ -162,7 +174,7 @@ __device__ __forceinline__ void tile_symmetric(const float2* __restrict__ Y, int
 // Direct tile: rows of block a against every valid column of block b.
 // SELF (a == b) masks the i == j term by index; MASK_I masks rows past n
 // (only the last block is partial).  Full off-diagonal tiles run unmasked.
-template <int R, bool SPLIT, bool SELF, bool MASK_I>
+template <int R, bool SPLIT, bool SELF, bool MASK_I, bool FORCES>
 __device__ __forceinline__ void tile_direct_body(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                                  float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                  int64_t item, int lane) {
@@ -198,22 +210,28 @@ __device__ __forceinline__ void tile_direct_body(const float2* __restrict__ Y, i
           w = keep ? w : 0.f;
         }
         zs += w;
-        const float w2 = w * w;
-        rix[r] = __builtin_fmaf(w2, dx, rix[r]);
-        riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+        if (FORCES) {
+          const float w2 = w * w;
+          rix[r] = __builtin_fmaf(w2, dx, rix[r]);
+          riy[r] = __builtin_fmaf(w2, dy, riy[r]);
+        }
       }
       if (SPLIT) z64 += (double)zs; else z32 += zs;
     }
+    if (FORCES) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      hix[r] += rix[r];
-      hiy[r] += riy[r];
-      rix[r] = riy[r] = 0.f;
+      for (int r = 0; r < R; ++r) {
+        hix[r] += rix[r];
+        hiy[r] += riy[r];
+        rix[r] = riy[r] = 0.f;
+      }
     }
   }
+  if (FORCES) {
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (vi[r]) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+    for (int r = 0; r < R; ++r)
+      if (vi[r]) part[((int64_t)a * nb + b) * T + r * kWave + lane] = make_float2(hix[r], hiy[r]);
+  }
   if (SPLIT) {
     const double z = wave_sum(z64);
     if (lane == 0) zpart[item] = z;
@@ -223,24 +241,24 @@ __device__ __forceinline__ void tile_direct_body(const float2* __restrict__ Y, i
   }
 }
 
-template <int R, bool SPLIT>
+template <int R, bool SPLIT, bool FORCES = true>
 __device__ __forceinline__ void tile_direct(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a, int32_t b,
                             float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                             int64_t item, int lane) {
   const bool partial_a = (int64_t)(a + 1) * (kWave * R) > n;
   if (a == b) {
-    if (partial_a) tile_direct_body<R, SPLIT, true, true>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
-    else tile_direct_body<R, SPLIT, true, false>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    if (partial_a) tile_direct_body<R, SPLIT, true, true, FORCES>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    else tile_direct_body<R, SPLIT, true, false, FORCES>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
   } else {
-    if (partial_a) tile_direct_body<R, SPLIT, false, true>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
-    else tile_direct_body<R, SPLIT, false, false>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    if (partial_a) tile_direct_body<R, SPLIT, false, true, FORCES>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
+    else tile_direct_body<R, SPLIT, false, false, FORCES>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
   }
 }
 
 // Diagonal tile (a, a) inside the symmetric kernel: one resident row per lane
 // per pass (few registers, so the symmetric path keeps its occupancy), every
 // ordered pair i != j, four interleaved partial sums per coordinate.
-template <int R, bool SPLIT>
+template <int R, bool SPLIT, bool FORCES = true>
 __device__ __forceinline__ void tile_diag_light(const float2* __restrict__ Y, int32_t n, int32_t nb, int32_t a,
                                 float2* __restrict__ part, double* __restrict__ zpart, float* __restrict__ zpart32,
                                 int64_t item, int lane) {
@@ -267,9 +285,11 @@ __device__ __forceinline__ void tile_diag_light(const float2* __restrict__ Y, in
           float w = student_w(dx, dy);
           w = (vi && jl + k != il) ? w : 0.f;
           az[k] += w;
-          const float w2 = w * w;
-          ax[k] = __builtin_fmaf(w2, dx, ax[k]);
-          ay[k] = __builtin_fmaf(w2, dy, ay[k]);
+          if (FORCES) {
+            const float w2 = w * w;
+            ax[k] = __builtin_fmaf(w2, dx, ax[k]);
+            ay[k] = __builtin_fmaf(w2, dy, ay[k]);
+          }
         }
       }
       for (; jl < j1; ++jl) {
@@ -278,16 +298,20 @@ __device__ __forceinline__ void tile_diag_light(const float2* __restrict__ Y, in
         float w = student_w(dx, dy);
         w = (vi && jl != il) ? w : 0.f;
         az[0] += w;
-        const float w2 = w * w;
-        ax[0] = __builtin_fmaf(w2, dx, ax[0]);
-        ay[0] = __builtin_fmaf(w2, dy, ay[0]);
+        if (FORCES) {
+          const float w2 = w * w;
+          ax[0] = __builtin_fmaf(w2, dx, ax[0]);
+          ay[0] = __builtin_fmaf(w2, dy, ay[0]);
+        }
       }
-      hx += (ax[0] + ax[1]) + (ax[2] + ax[3]);
-      hy += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+      if (FORCES) {
+        hx += (ax[0] + ax[1]) + (ax[2] + ax[3]);
+        hy += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+      }
       const float zc = (az[0] + az[1]) + (az[2] + az[3]);
       if (SPLIT) z64 += (double)zc; else z32 += zc;
     }
-    if (vi) part[((int64_t)a * nb + a) * T + il] = make_float2(hx, hy);
+    if (FORCES && vi) part[((int64_t)a * nb + a) * T + il] = make_float2(hx, hy);
   }
   if (SPLIT) {
     const double z = wave_sum(z64);
@@ -327,6 +351,48 @@ __global__ __launch_bounds__(kBlock, repulse_min_waves<R>()) void k_repulse(cons
   } else {
     tile_direct<R, SPLIT>(Y, n, nb, a, b, part, zpart, zpart32, item, lane);
   }
+}
+
+// Z alone (no forces, no partials written): the weights and their sums in the
+// order k_repulse uses, so the Z partials are bitwise those of the force pass.
+template <int R, bool SPLIT, bool SYM>
+__global__ __launch_bounds__(kBlock, repulse_min_waves<R>()) void k_zonly(const float2* __restrict__ Y, int32_t n,
+                                                                          int32_t nb, const int2* __restrict__ items,
+                                                                          int64_t n_items, double* __restrict__ zpart,
+                                                                          float* __restrict__ zpart32) {
+  const int64_t item =
+      (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int2 ab = items[item];
+  const int32_t a = __builtin_amdgcn_readfirstlane(ab.x), b = __builtin_amdgcn_readfirstlane(ab.y);
+  if (SYM) {
+    if (a != b) tile_symmetric<R, SPLIT, false>(Y, n, nb, a, b, nullptr, zpart, zpart32, item, lane);
+    else tile_diag_light<R, SPLIT, false>(Y, n, nb, a, nullptr, zpart, zpart32, item, lane);
+  } else {
+    tile_direct<R, SPLIT, false>(Y, n, nb, a, b, nullptr, zpart, zpart32, item, lane);
+  }
+}
+
+template <int R>
+hipError_t launch_zonly_r(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s) {
+  const RepulsionPlan& p = ws.plan;
+  const dim3 grid((unsigned)((p.items + kWavesPerBlock - 1) / kWavesPerBlock));
+  const bool split = precision != TSGNE_PREC_FP32;
+  const bool sym = p.variant == TSGNE_REPULSION_SYMMETRIC;
+  if (split && sym)
+    hipLaunchKernelGGL((k_zonly<R, true, true>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.zpart,
+                       ws.zpart32);
+  else if (split)
+    hipLaunchKernelGGL((k_zonly<R, true, false>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.zpart,
+                       ws.zpart32);
+  else if (sym)
+    hipLaunchKernelGGL((k_zonly<R, false, true>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items, ws.zpart,
+                       ws.zpart32);
+  else
+    hipLaunchKernelGGL((k_zonly<R, false, false>), grid, dim3(kBlock), 0, s, Y, n, p.nb, ws.items, p.items,
+                       ws.zpart, ws.zpart32);
+  return hipGetLastError();
 }
 
 template <int R>
@@ -401,10 +467,19 @@ __device__ __forceinline__ void zsum_block(const double* __restrict__ zpart, con
   if (t == 0) *Z = SPLIT ? sh64[0] : (double)sh32[0];
 }
 
+// tstep (nullable) is the device step counter of a run: {next step, step being
+// run}.  The Z sum, the one single-workgroup kernel of a step and the first
+// after the repulsion, takes the step's index from it for the kernels after it.
 template <bool SPLIT>
 __global__ __launch_bounds__(kZThreads) void k_zsum(const double* __restrict__ zpart, const float* __restrict__ zpart32,
-                                                    int64_t n_items, double* __restrict__ Z) {
+                                                    int64_t n_items, double* __restrict__ Z,
+                                                    int32_t* __restrict__ tstep) {
   zsum_block<SPLIT>(zpart, zpart32, n_items, Z);
+  if (tstep && threadIdx.x == 0) {
+    const int32_t t = tstep[0];
+    tstep[1] = t;
+    tstep[0] = t + 1;
+  }
 }
 
 // Attraction sum_j p_ij w_ij (y_i - y_j) over the stored entries of row i
@@ -562,14 +637,23 @@ __device__ __forceinline__ void update_row(const float2* __restrict__ part, int3
   G[i] = gn;
 }
 
+// With sched.tstep set, alpha and the momentum come from the step index on the
+// device (early exaggeration while t < t_ee), so that a captured step can be
+// replayed; otherwise the host's values are used.
 template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_update(const float2* __restrict__ part, int32_t nb, int32_t T,
                                                    const double2* __restrict__ attract, const double* __restrict__ Zp,
                                                    int32_t n, float2* __restrict__ Y, float2* __restrict__ U,
                                                    float2* __restrict__ G, float alpha, float momentum, float eta,
-                                                   float min_gain, int do_update, float2* __restrict__ grad_out) {
+                                                   float min_gain, int do_update, float2* __restrict__ grad_out,
+                                                   StepSchedule sched) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  if (sched.tstep) {
+    const bool early = sched.tstep[1] < sched.exaggeration_iters;
+    alpha = early ? sched.early_exaggeration : 1.0f;
+    momentum = early ? sched.momentum_early : sched.momentum_late;
+  }
   update_row<SPLIT>(part, nb, T, attract, *Zp, i, Y, U, G, alpha, momentum, eta, min_gain, do_update != 0, grad_out);
 }
 
@@ -661,10 +745,22 @@ __global__ __launch_bounds__(kBlock) void k_batch_advance(const BatchDesc* __res
 // per-thread sums, tree per block, then one block over the block sums.
 constexpr int kKLThreads = 256;
 
+// KL sampling inside a run (trace != nullptr): the step being run (tstep[1])
+// holds the layout after t steps; it is sampled when t is a positive multiple
+// of kl_every, into trace[t / kl_every - 1], with the Z this step has just
+// summed at that layout.  Other steps return at once.
+__device__ __forceinline__ bool kl_skip(const int32_t* tstep, int32_t kl_every) {
+  if (!tstep) return false;
+  const int32_t t = tstep[1];
+  return t <= 0 || t % kl_every != 0;
+}
+
 __global__ __launch_bounds__(kKLThreads) void k_kl_edges(const int32_t* __restrict__ row_of,
                                                          const int32_t* __restrict__ col, const float* __restrict__ P,
                                                          const float2* __restrict__ Y, int64_t nnz,
-                                                         const double* __restrict__ Zp, double* __restrict__ klpart) {
+                                                         const double* __restrict__ Zp, double* __restrict__ klpart,
+                                                         const int32_t* __restrict__ tstep, int32_t kl_every) {
+  if (kl_skip(tstep, kl_every)) return;
   __shared__ double sh[kKLThreads];
   const double logZ = *Zp > 0.0 ? log(*Zp) : 0.0;
   double acc = 0.0;
@@ -686,7 +782,9 @@ __global__ __launch_bounds__(kKLThreads) void k_kl_edges(const int32_t* __restri
 }
 
 __global__ __launch_bounds__(kKLThreads) void k_kl_final(const double* __restrict__ klpart, int32_t nparts,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ out, const int32_t* __restrict__ tstep,
+                                                         int32_t kl_every, double* __restrict__ trace) {
+  if (kl_skip(tstep, kl_every)) return;
   __shared__ double sh[kKLThreads];
   double acc = 0.0;
   for (int32_t k = threadIdx.x; k < nparts; k += kKLThreads) acc += klpart[k];
@@ -696,7 +794,10 @@ __global__ __launch_bounds__(kKLThreads) void k_kl_final(const double* __restric
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sh[0];
+  if (threadIdx.x == 0) {
+    *out = sh[0];
+    if (trace) trace[tstep ? tstep[1] / kl_every - 1 : 0] = sh[0];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_nonfinite(const float2* __restrict__ Y, int32_t n,
@@ -779,11 +880,27 @@ hipError_t launch_repulsion(const Workspace& ws, int32_t n, const float2* Y, int
   }
 }
 
-hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s) {
+hipError_t launch_zonly(const Workspace& ws, int32_t n, const float2* Y, int precision, hipStream_t s) {
+  switch (ws.plan.R) {
+    case 1: return launch_zonly_r<1>(ws, n, Y, precision, s);
+    case 2: return launch_zonly_r<2>(ws, n, Y, precision, s);
+    case 4: return launch_zonly_r<4>(ws, n, Y, precision, s);
+    case 8: return launch_zonly_r<8>(ws, n, Y, precision, s);
+    case 16: return launch_zonly_r<16>(ws, n, Y, precision, s);
+    case 12: return launch_zonly_r<12>(ws, n, Y, precision, s);
+    case 14: return launch_zonly_r<14>(ws, n, Y, precision, s);
+    case 15: return launch_zonly_r<15>(ws, n, Y, precision, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_zsum(const Workspace& ws, int precision, hipStream_t s, int32_t* tstep) {
   if (precision == TSGNE_PREC_FP32)
-    hipLaunchKernelGGL(k_zsum<false>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z);
+    hipLaunchKernelGGL(k_zsum<false>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z,
+                       tstep);
   else
-    hipLaunchKernelGGL(k_zsum<true>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z);
+    hipLaunchKernelGGL(k_zsum<true>, dim3(1), dim3(kZThreads), 0, s, ws.zpart, ws.zpart32, ws.plan.items, ws.Z,
+                       tstep);
   return hipGetLastError();
 }
 
@@ -809,27 +926,29 @@ hipError_t launch_attract(const tsgne_graph* g, const float2* Y, int precision, 
 
 hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gains, float alpha, float momentum,
                          float eta, float min_gain, int precision, bool do_update, float2* grad_out, double* Z_out,
-                         hipStream_t s) {
+                         hipStream_t s, const StepSchedule& sched) {
   const Workspace& ws = g->ws;
   const unsigned nbk = blocks_for(g->n, kBlock);
   if (precision == TSGNE_PREC_FP32)
     hipLaunchKernelGGL(k_update<false>, dim3(nbk), dim3(kBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, ws.attract,
-                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out);
+                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out, sched);
   else
     hipLaunchKernelGGL(k_update<true>, dim3(nbk), dim3(kBlock), 0, s, ws.part, ws.plan.nb, ws.plan.T, ws.attract,
-                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out);
+                       ws.Z, g->n, Y, U, gains, alpha, momentum, eta, min_gain, (int)do_update, grad_out, sched);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !Z_out) return e;
   return hipMemcpyAsync(Z_out, ws.Z, sizeof(double), hipMemcpyDeviceToDevice, s);
 }
 
-hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s) {
+hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s, const int32_t* tstep, int32_t kl_every,
+                     double* trace) {
   const Workspace& ws = g->ws;
   hipLaunchKernelGGL(k_kl_edges, dim3(ws.kl_blocks), dim3(kKLThreads), 0, s, g->row_of, g->col, g->P, Y, g->nnz, ws.Z,
-                     ws.klpart);
+                     ws.klpart, tstep, kl_every);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kKLThreads), 0, s, ws.klpart, ws.kl_blocks, ws.klout);
+  hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kKLThreads), 0, s, ws.klpart, ws.kl_blocks, ws.klout, tstep, kl_every,
+                     trace);
   return hipGetLastError();
 }
 

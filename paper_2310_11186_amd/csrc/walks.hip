@@ -13,7 +13,8 @@
 // order).  The endpoints become 64-bit keys i*n + j and j*n + i; a radix
 // sort over the bits those need and a run-length encoding give the canonical
 // symmetric CSR and the counts.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_run_length_encode.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -193,14 +194,14 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
   int end_bit = 1;
   while (end_bit < 64 && (no_key >> end_bit) != 0) ++end_bit;  // keys are at most n*n
   size_t sort_bytes = 0, rle_bytes = 0;
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                              (int)n_keys, 0, end_bit, s),
+  TSGNE_HIP(rocprim::radix_sort_keys(nullptr, sort_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (int)n_keys, 0,
+                                    end_bit, s),
             "size sort");
-  TSGNE_HIP(hipcub::DeviceRunLengthEncode::Encode(nullptr, rle_bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                                  (int32_t*)nullptr, (int64_t*)nullptr, (int)n_keys, s),
+  TSGNE_HIP(rocprim::run_length_encode(nullptr, rle_bytes, (uint64_t*)nullptr, (unsigned int)n_keys, (uint64_t*)nullptr,
+                                      (int32_t*)nullptr, (int64_t*)nullptr, s),
             "size run-length encoding");
   // one allocation: CSR check | C | keys | sorted keys | run keys | run counts
-  //                 | run count | new row_ptr | new col | new P | cub scratch
+  //                 | run count | new row_ptr | new col | new P | sort scratch
   size_t o = 0;
   const size_t o_chk = o;
   o = align256(o + validate_csr_bytes(n, nnz));
@@ -240,7 +241,7 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
   int32_t* const new_rp = reinterpret_cast<int32_t*>(base + o_rp);
   int32_t* const new_col = reinterpret_cast<int32_t*>(base + o_col);
   float* const new_P = reinterpret_cast<float*>(base + o_P);
-  void* const cub_tmp = base + o_tmp;
+  void* const sort_tmp = base + o_tmp;
 
   if (nnz > 0) {
     if (d % 4 == 0)
@@ -254,10 +255,10 @@ tsgne_status tsgne_build_P_walks(int32_t n, int64_t nnz, const int32_t* row_ptr_
                      length, seed, keys);
   TSGNE_HIP(hipGetLastError(), "launch walks");
   size_t bytes = sort_bytes;
-  TSGNE_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, bytes, keys, sorted, (int)n_keys, 0, end_bit, s),
+  TSGNE_HIP(rocprim::radix_sort_keys(sort_tmp, bytes, keys, sorted, (int)n_keys, 0, end_bit, s),
             "sort endpoints");
   bytes = rle_bytes;
-  TSGNE_HIP(hipcub::DeviceRunLengthEncode::Encode(cub_tmp, bytes, sorted, runs, counts, n_runs, (int)n_keys, s),
+  TSGNE_HIP(rocprim::run_length_encode(sort_tmp, bytes, sorted, (unsigned int)n_keys, runs, counts, n_runs, s),
             "count endpoints");
   int64_t host_runs = 0;
   TSGNE_HIP(hipMemcpyAsync(&host_runs, n_runs, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read run count");

@@ -360,80 +360,61 @@ def test_full_run_kl_and_final_gradient(gpu, c1_cases):
     assert row_error_ratio(gg, og, oY32, oZ)[0] <= ROW_TOL
 
 
-def test_run_equals_steps_and_is_deterministic(gpu):
+@pytest.mark.parametrize("n_iter,t_ee", [(25, 10), (75, 40), (96, 64), (64, 0)])
+def test_run_equals_steps_and_is_deterministic(gpu, n_iter, t_ee):
+    # 25 steps: no full captured chunk (32 steps), all launched directly; 75:
+    # two replays then 11 direct steps, the exaggeration switch inside the
+    # second replay; 96: three replays, the switch at a chunk boundary; 64:
+    # no exaggeration at all
     c = make_case("dcsbm", 3001, gpu, 30.0, seed=4)
-    p = tsgne.tsgne_params_default(exaggeration_iters=10, learning_rate=100.0)
+    p = tsgne.tsgne_params_default(exaggeration_iters=t_ee, learning_rate=100.0)
     n = c.n
     Yr = c.Y(c.gi.Y0)
-    tsgne.tsgne_run(c.graph, Yr, 25, p)
-    Ys, _, _ = gpu_steps(c, c.gi.Y0, np.zeros((n, 2)), np.ones((n, 2)), 0, 25, p)
+    tsgne.tsgne_run(c.graph, Yr, n_iter, p)
+    Ys, _, _ = gpu_steps(c, c.gi.Y0, np.zeros((n, 2)), np.ones((n, 2)), 0, n_iter, p)
     assert np.array_equal(Yr.cpu().numpy(), Ys)
     Yr2 = c.Y(c.gi.Y0)
-    tsgne.tsgne_run(c.graph, Yr2, 25, p)
+    tsgne.tsgne_run(c.graph, Yr2, n_iter, p)
     assert np.array_equal(Yr.cpu().numpy(), Yr2.cpu().numpy())
 
 
-def test_kl_matches_oracle(gpu):
-    c = make_case("sbm2k", 2000, gpu, 30.0)
-    for name, Y in states(2000, 3).items():
-        kl = tsgne.tsgne_kl(c.graph, c.Y(Y))
-        okl = oracle.kl(c.orp, c.ocol, c.oP, Y.astype(np.float64))
-        assert abs(kl - okl) <= KL_TOL, (name, kl, okl)
-
-
-def test_run_kl_trace(gpu):
-    c = make_case("sbm", 900, gpu, 30.0, seed=8)
-    p = tsgne.tsgne_params_default(exaggeration_iters=10, learning_rate=60.0, kl_every=10)
-    Y = c.Y(c.gi.Y0)
-    trace = tsgne.tsgne_run(c.graph, Y, 30, p)
-    assert trace.shape == (3,)
-    assert trace[-1] == pytest.approx(tsgne.tsgne_kl(c.graph, Y), rel=1e-12)
-    oY, _, _, otrace = oracle.run(c.orp, c.ocol, c.oP, c.gi.Y0, n_steps=30, exaggeration_iters=10, eta=60.0,
-                                  kl_every=10)
-    np.testing.assert_allclose(trace, otrace, rtol=1e-5)
-
-
-def test_graphs_on_concurrent_threads(gpu):
-    """Different graphs used at once from different host threads, each on its
-    own stream: every layout equals the same run done alone, bit for bit."""
-    import threading
-
+@pytest.mark.parametrize("n_iter,kl_every", [(100, 10), (120, 40), (70, 7), (50, 100)])
+def test_run_kl_trace_equals_kl_of_steps(gpu, n_iter, kl_every):
+    """Samples taken inside the replayed steps (with the Z each step sums)
+    equal tsgne_kl at the same layouts, bit for bit; the last one is taken
+    after the run."""
     import torch
-    gis = [synth.small_sbm(n, 3, 5.0, 8, 40 + k) for k, n in enumerate([900, 2500, 1700, 3100])]
-    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0)
-    graphs = []
-    for gi in gis:
-        rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
-        graphs.append(tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
-                                          torch.from_numpy(gi.X).to(gpu), 30.0))
-    alone = []
-    for gi, g in zip(gis, graphs):
-        Y = torch.from_numpy(gi.Y0).to(gpu)
-        tsgne.tsgne_run(g, Y, 80, p)
-        alone.append(Y.cpu().numpy())
-    outs = [None] * len(gis)
-    errors = []
+    c = make_case("sbm", 1500, gpu, 30.0, seed=12)
+    p = tsgne.tsgne_params_default(exaggeration_iters=30, learning_rate=80.0, kl_every=kl_every)
+    Y = c.Y(c.gi.Y0)
+    trace = tsgne.tsgne_run(c.graph, Y, n_iter, p)
+    assert trace.shape == (n_iter // kl_every,)
+    Ys, U, G = c.Y(c.gi.Y0), torch.zeros_like(Y), torch.ones_like(Y)
+    want = []
+    for t in range(n_iter):
+        tsgne.tsgne_step(c.graph, Ys, U, G, t, p)
+        if (t + 1) % kl_every == 0:
+            want.append(tsgne.tsgne_kl(c.graph, Ys))
+    assert np.array_equal(Y.cpu().numpy(), Ys.cpu().numpy())
+    np.testing.assert_array_equal(trace, np.array(want))
 
-    def work(k):
-        try:
-            s = torch.cuda.Stream(device=gpu)
-            with torch.cuda.stream(s):   # every copy and run of this thread on its own stream
-                Y = torch.from_numpy(gis[k].Y0).to(gpu)
-                for _ in range(3):       # several runs per thread, overlapping the other threads'
-                    Yk = Y.clone()
-                    tsgne.tsgne_run(graphs[k], Yk, 80, p, stream=s)
-                    outs[k] = Yk.cpu().numpy()
-            s.synchronize()
-        except Exception as e:   # reported below, in the main thread
-            errors.append(e)
 
-    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(gis))]
-    for t in threads:
-        t.start()
-    for t in threads:
-        t.join()
-    assert not errors, errors
-    for a, b in zip(alone, outs):
-        assert np.array_equal(a, b)
-    for g in graphs:
-        g.close()
+def test_run_with_phase_timing(gpu):
+    """With phase timing on, a run launches its steps one by one (every launch
+    between its own events): every launch is counted and the layout is
+    bitwise the replayed run's."""
+    import torch
+    c = make_case("dcsbm", 3001, gpu, 30.0, seed=4)
+    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=100.0)
+    g = c.graph
+    Yg = c.Y(c.gi.Y0)
+    tsgne.tsgne_run(g, Yg, 80, p)
+    g.set_timing(True)
+    Y = c.Y(c.gi.Y0)
+    tsgne.tsgne_run(g, Y, 80, p)
+    tm = g.timing()
+    g.set_timing(False)
+    for phase in ("repulsion", "zsum", "attract", "update"):
+        ms, launches = tm[phase]
+        assert launches == 80 and ms > 0.0, (phase, tm[phase])
+    assert np.array_equal(Y.cpu().numpy(), Yg.cpu().numpy())
