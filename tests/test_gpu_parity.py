@@ -23,7 +23,7 @@ import numpy as np
 import pytest
 
 import oracle
-from bars import GRAD_TOL, KL_TOL, P_TOL, ROW_TOL, Z_TOL, rel_l2, row_error_ratio
+from bars import GRAD_TOL, P_TOL, ROW_TOL, Z_TOL, kl_close, rel_l2, row_error_ratio
 from paper_2310_11186_amd import synth, tsgne
 
 pytestmark = pytest.mark.gpu
@@ -418,3 +418,69 @@ def test_run_with_phase_timing(gpu):
         ms, launches = tm[phase]
         assert launches == 80 and ms > 0.0, (phase, tm[phase])
     assert np.array_equal(Y.cpu().numpy(), Yg.cpu().numpy())
+
+
+def test_kl_matches_oracle(gpu):
+    c = make_case("sbm2k", 2000, gpu, 30.0)
+    for name, Y in states(2000, 3).items():
+        kl = tsgne.tsgne_kl(c.graph, c.Y(Y))
+        okl = oracle.kl(c.orp, c.ocol, c.oP, Y.astype(np.float64))
+        assert kl_close(kl, okl), (name, kl, okl)
+
+
+def test_run_kl_trace(gpu):
+    c = make_case("sbm", 900, gpu, 30.0, seed=8)
+    p = tsgne.tsgne_params_default(exaggeration_iters=10, learning_rate=60.0, kl_every=10)
+    Y = c.Y(c.gi.Y0)
+    trace = tsgne.tsgne_run(c.graph, Y, 30, p)
+    assert trace.shape == (3,)
+    assert trace[-1] == pytest.approx(tsgne.tsgne_kl(c.graph, Y), rel=1e-12)
+    oY, _, _, otrace = oracle.run(c.orp, c.ocol, c.oP, c.gi.Y0, n_steps=30, exaggeration_iters=10, eta=60.0,
+                                  kl_every=10)
+    np.testing.assert_allclose(trace, otrace, rtol=1e-5)
+
+
+def test_graphs_on_concurrent_threads(gpu):
+    """Different graphs used at once from different host threads, each on its
+    own stream: every layout equals the same run done alone, bit for bit."""
+    import threading
+
+    import torch
+    gis = [synth.small_sbm(n, 3, 5.0, 8, 40 + k) for k, n in enumerate([900, 2500, 1700, 3100])]
+    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0)
+    graphs = []
+    for gi in gis:
+        rp, col = tsgne.tsgne_csr_from_edges(gi.n, gi.edges)
+        graphs.append(tsgne.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
+                                          torch.from_numpy(gi.X).to(gpu), 30.0))
+    alone = []
+    for gi, g in zip(gis, graphs):
+        Y = torch.from_numpy(gi.Y0).to(gpu)
+        tsgne.tsgne_run(g, Y, 80, p)
+        alone.append(Y.cpu().numpy())
+    outs = [None] * len(gis)
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream(device=gpu)
+            with torch.cuda.stream(s):   # every copy and run of this thread on its own stream
+                Y = torch.from_numpy(gis[k].Y0).to(gpu)
+                for _ in range(3):       # several runs per thread, overlapping the other threads'
+                    Yk = Y.clone()
+                    tsgne.tsgne_run(graphs[k], Yk, 80, p, stream=s)
+                    outs[k] = Yk.cpu().numpy()
+            s.synchronize()
+        except Exception as e:   # reported below, in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(gis))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for a, b in zip(alone, outs):
+        assert np.array_equal(a, b)
+    for g in graphs:
+        g.close()
