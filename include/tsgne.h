@@ -417,6 +417,23 @@ TSGNE_API tsgne_status tsgne_run(tsgne_graph* g, float* Y_d, int32_t n_iter, con
 TSGNE_API tsgne_status tsgne_kl(tsgne_graph* g, const float* Y_d, double* kl_h, void* stream);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): tsgne_kl without any allocation
+ * and without synchronising.  The KL of the layout Y_d (float32[n][2],
+ * device) lands in *kl_d (float64, device, caller-owned) in stream order.
+ * It runs the kernels of tsgne_kl with the same repulsion plan (the graph's
+ * workspace plan, or the automatic one before the graph's first step), so
+ * the value is bitwise tsgne_kl's.  Their scratch (tile list, Z partials, KL
+ * partials: 16 bytes per repulsion tile plus 8 KiB) lives in a 32 MiB device
+ * array that each GPU holds until the process ends (up to about 2 million
+ * nodes); a larger graph is refused with E_INVAL and a message giving the
+ * size.  Every call on one GPU uses that GPU's one array: calls that overlap
+ * on a GPU (different streams, threads or graphs) race and must be ordered
+ * by the caller.  Errors: E_INVAL, E_DEVICE (a launch failed).
+ */
+TSGNE_API tsgne_status tsgne_kl_noalloc(tsgne_graph* g, const float* Y_d, double* kl_d, void* stream);
+
+/*
  * Advances many independent graphs together (the same optimiser as
  * tsgne_run, eqs. (4)-(5) per graph).  graphs[k] / Y_d[k] (float32[n_k][2], in:
  * Y0, out: final layout) for k < count; graph k takes n_iter[k] steps

@@ -273,6 +273,9 @@ hipError_t launch_update(const tsgne_graph* g, float2* Y, float2* U, float2* gai
 // trace set, also into trace[0].
 hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s, const int32_t* tstep = nullptr,
                      int32_t kl_every = 0, double* trace = nullptr);
+// KL of g's P at Y with the Z, partials and output of a given workspace view
+// (ws.Z, ws.klpart[ws.kl_blocks], ws.klout).
+hipError_t launch_kl_ws(const tsgne_graph* g, const Workspace& ws, const float2* Y, hipStream_t s);
 hipError_t launch_nonfinite_check(const float2* Y, int32_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_batch_step(const BatchPlan& bp, const tsgne_params& p, hipStream_t s);
 

@@ -952,6 +952,16 @@ hipError_t launch_kl(const tsgne_graph* g, const float2* Y, hipStream_t s, const
   return hipGetLastError();
 }
 
+hipError_t launch_kl_ws(const tsgne_graph* g, const Workspace& ws, const float2* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_kl_edges, dim3(ws.kl_blocks), dim3(kKLThreads), 0, s, g->row_of, g->col, g->P, Y, g->nnz, ws.Z,
+                     ws.klpart, nullptr, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kKLThreads), 0, s, ws.klpart, ws.kl_blocks, ws.klout, nullptr, 0,
+                     nullptr);
+  return hipGetLastError();
+}
+
 template <int R>
 hipError_t launch_batch_repulse_r(const BatchPlan& bp, bool split, hipStream_t s) {
   const dim3 grid((unsigned)((bp.n_items + kWavesPerBlock - 1) / kWavesPerBlock));

@@ -43,7 +43,7 @@ EXPORTED = (
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
     "tsgne_build_P_walks", "tsgne_locality_order", "tsgne_permute_graph", "tsgne_permute_rows",
     "tsgne_graph_from_host_P", "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
-    "tsgne_kl", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
+    "tsgne_kl", "tsgne_kl_noalloc", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
     "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
     "tsgne_server_destroy", "tsgne_shard_create", "tsgne_shard_info", "tsgne_shard_repulsion", "tsgne_shard_set_timing",
@@ -155,6 +155,7 @@ def lib():
             "tsgne_step": (st, [vp, vp, vp, vp, i32, P, vp, vp, vp]),
             "tsgne_run": (st, [vp, vp, i32, P, vp, vp]),
             "tsgne_kl": (st, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_kl_noalloc": (st, [vp, vp, vp, vp]),
             "tsgne_attraction": (st, [vp, vp, i32, vp, vp]),
             "tsgne_batch_run": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32), i32, P, vp]),
             "tsgne_autotune": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.POINTER(i32),
@@ -570,6 +571,17 @@ def tsgne_kl(g: Graph, Y, stream=None) -> float:
     out = ctypes.c_double(0.0)
     _check(lib().tsgne_kl(g.handle, _ptr(Y), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def tsgne_kl_noalloc(g: Graph, Y, out, stream=None):
+    """KL at Y into out (float64[1] device tensor, caller-owned), in stream
+    order, with no allocation and no synchronisation; returns out."""
+    import torch
+    n, _ = g.info()
+    _require(Y, torch.float32, (n, 2), "Y")
+    _require(out, torch.float64, (1,), "out")
+    _check(lib().tsgne_kl_noalloc(g.handle, _ptr(Y), _ptr(out), _stream(stream)))
+    return out
 
 
 def tsgne_batch_run(graphs, Ys, n_iter, params: tsgne_params, stream=None) -> None:
