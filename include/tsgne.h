@@ -494,21 +494,32 @@ typedef struct tsgne_server_config {
   int32_t max_active;      /* requests advanced together (default 64) */
   int32_t max_queue;       /* waiting requests before submit returns E_BUSY */
   int32_t steps_per_round; /* most steps a request takes per round (default 64) */
-  int32_t tile_rows;       /* repulsion tile rows: 0 (default) = per request (8 below 131072 nodes, the
-                              single-graph plan's choice above, and for every request when max_active is 1);
-                              1, 2, 4, 8, 12, 14, 15 or 16 = for every request */
+  int32_t tile_rows;       /* repulsion tile rows: 0 (default) = per request, the single-graph plan's choice
+                              (its layout equals its own tsgne_run); 1, 2, 4, 8, 12, 14, 15 or 16 = for every
+                              request */
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
   float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
   float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared
                               by rest_policy (default 0.5; 0 = the whole round by rest_policy); bounds how far
                               small arrivals can slow the request that has waited longest */
-  int32_t rest_policy;     /* how the rest of a round is shared: TSGNE_SHARE_EQUAL (default) in equal parts,
-                              TSGNE_SHARE_SMALLEST_FIRST to the requests with the least remaining work first
-                              (each as many steps as a round allows until the time runs out) */
+  int32_t rest_policy;     /* how a round is shared: TSGNE_SHARE_SHORT_FIRST (default): requests with at most
+                              long_ms of GPU time left take what they need first (least remaining first), and
+                              long requests run one at a time in submission order with the rest (the others
+                              paused); while a long request runs, the short ones take at most short_share of
+                              a round and only as much as the long one is ahead of its estimated finish in
+                              the one-at-a-time schedule; with oldest_share: TSGNE_SHARE_EQUAL shares the rest in
+                              equal parts, TSGNE_SHARE_SMALLEST_FIRST to the requests with the least
+                              remaining work first (each as many steps as a round allows until the time runs
+                              out) */
+  float long_ms;           /* TSGNE_SHARE_SHORT_FIRST: GPU time left (estimated from the measured pair rate)
+                              above which a request is long (default 150) */
+  float short_share;       /* TSGNE_SHARE_SHORT_FIRST: most of a round the short requests take while a long
+                              one waits, in (0, 1) (default 0.3) */
 } tsgne_server_config;
 
 #define TSGNE_SHARE_EQUAL 0
 #define TSGNE_SHARE_SMALLEST_FIRST 1
+#define TSGNE_SHARE_SHORT_FIRST 2
 
 typedef struct tsgne_request {
   int32_t n;             /* nodes */
@@ -527,6 +538,9 @@ typedef struct tsgne_server_stats {
   int64_t hbm_in_use, hbm_budget; /* bytes (estimated footprints) */
   int64_t rounds;
   double busy_s;                  /* time spent in rounds */
+  double admit_s;                 /* worker time spent admitting requests (uploads and affinities; mostly
+                                     while a round runs on the GPU) */
+  double plan_s;                  /* worker time spent between rounds on plans, captures and shares */
   double latency_p50_ms, latency_p99_ms, latency_mean_ms; /* submission to completion, completed requests */
   double layouts_per_s;           /* completed / (last completion - first submission) */
 } tsgne_server_stats;

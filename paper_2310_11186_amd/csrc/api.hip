@@ -200,19 +200,15 @@ tsgne_status graph_structure(int32_t n, int64_t nnz, const int32_t* row_ptr_d, c
     ~Cleanup() { free_graph(g); }
   } guard{g};
 
-  uint32_t* err = nullptr;
-  int32_t* counters = nullptr;
-  int2* partial = nullptr;
-  struct Scratch {
-    uint32_t*& err;
-    int32_t*& counters;
-    int2*& partial;
-    ~Scratch() {
-      dfree(err);
-      dfree(counters);
-      dfree(partial);
-    }
-  } scratch{err, counters, partial};
+  // temporaries from the stream-ordered pool (freeing them does not wait for
+  // other streams' work, unlike hipFree)
+  ScratchBlock tmp;
+  tmp.s = s;
+  const size_t o_counters = 256, o_partial = 512;
+  TSGNE_HIP(scratch_alloc(&tmp.p, o_partial + sizeof(int2) * (size_t)row_check_blocks(n), s), "allocate CSR checks");
+  uint32_t* err = static_cast<uint32_t*>(tmp.p);
+  int32_t* counters = reinterpret_cast<int32_t*>(static_cast<char*>(tmp.p) + o_counters);
+  int2* partial = reinterpret_cast<int2*>(static_cast<char*>(tmp.p) + o_partial);
 
   const int32_t heavy_cap = (int32_t)std::min<int64_t>(n, nnz / (kHeavyDegree + 1) + 1);
   TSGNE_HIP(dalloc(&g->row_ptr, (size_t)n + 1), "allocate row_ptr");
@@ -222,9 +218,6 @@ tsgne_status graph_structure(int32_t n, int64_t nnz, const int32_t* row_ptr_d, c
   TSGNE_HIP(dalloc(&g->P, (size_t)nnz), "allocate P");
   TSGNE_HIP(dalloc(&g->beta, (size_t)n), "allocate beta");
   TSGNE_HIP(dalloc(&g->heavy, (size_t)heavy_cap), "allocate heavy rows");
-  TSGNE_HIP(dalloc(&err, 1), "allocate error word");
-  TSGNE_HIP(dalloc(&counters, 2), "allocate counters");
-  TSGNE_HIP(dalloc(&partial, (size_t)row_check_blocks(n)), "allocate row counts");
 
   TSGNE_HIP(hipMemcpyAsync(g->row_ptr, row_ptr_d, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s),
             "copy row_ptr");
@@ -597,18 +590,12 @@ tsgne_status tsgne_build_P(int32_t n, int64_t nnz, const int32_t* row_ptr_d, con
   g->d = d;
   g->perplexity = perplexity;
 
-  double* D = nullptr;
-  double* pcond = nullptr;
-  struct Scratch {
-    double*& D;
-    double*& pcond;
-    ~Scratch() {
-      dfree(D);
-      dfree(pcond);
-    }
-  } scratch{D, pcond};
-  TSGNE_HIP(dalloc(&D, (size_t)nnz), "allocate distances");
-  TSGNE_HIP(dalloc(&pcond, (size_t)nnz), "allocate conditional affinities");
+  ScratchBlock tmp;
+  tmp.s = s;
+  const size_t o_pcond = ((size_t)std::max<int64_t>(nnz, 1) * sizeof(double) + 255) & ~(size_t)255;
+  TSGNE_HIP(scratch_alloc(&tmp.p, 2 * o_pcond, s), "allocate distances and conditional affinities");
+  double* D = static_cast<double*>(tmp.p);
+  double* pcond = reinterpret_cast<double*>(static_cast<char*>(tmp.p) + o_pcond);
 
   // Distances, calibration, symmetrisation.
   TSGNE_HIP(launch_sqdist(g->row_of, g->col, nnz, X_d, d, D, s), "launch distances");

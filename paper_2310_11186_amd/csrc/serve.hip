@@ -1,17 +1,19 @@
 // Layout server: continuous batching of t-SGNE requests on one GPU.
 //
 // Requests are copied in at submission and queued.  A worker thread owns all
-// device work: between rounds it admits queued requests while their estimated
-// device footprint fits the budget (building their affinities), then advances
-// every active request by its share of the round (at most `steps_per_round`
-// steps) in one captured batched sequence (each request at its own step
-// index), and completes the requests that reached n_iter (layout copied out,
-// memory released).  Requests are grouped by tile size, one batched plan per
-// group, the groups running on parallel branches of each captured round, each
-// branch as long as its own group's largest share.  Every request's arithmetic and
-// reduction order depend only on itself and its tile size (a function of its
-// size, or the server's fixed choice), so its layout is the same alone or in
-// any mix.
+// device work.  It runs rounds: each active request is given a number of
+// steps (its share of the round's target time, by the share policy; by
+// default short requests first and long ones one at a time in submission
+// order), and every group of requests with the same tile size replays a
+// captured chunk of batched steps (each request at its own step index,
+// pausing on the device at its allotment) on its own branch stream, the
+// groups running together.  While a round runs, queued requests are admitted
+// as their estimated device footprint fits the budget (their affinities built
+// on a stream of their own); they join the next round.  Requests that reached
+// n_iter complete at the round's end (layout copied out, memory released).
+// Every request's arithmetic and reduction order depend only on itself and
+// its tile size (a function of its size, or the server's fixed choice), so
+// its layout is the same alone or in any mix.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -48,6 +50,9 @@ struct Request {
   std::vector<float> X, Y0, Y;
   size_t footprint = 0;
   Clock::time_point t_submit, t_admit, t_done;
+  // when this request would finish if every request ran alone in submission
+  // order (estimated at admission, in that order; see tsgne_server::fifo_due)
+  Clock::time_point fifo_due;
   bool admitted = false;
   bool done = false, cancel = false;
   tsgne_status status = TSGNE_OK;
@@ -59,17 +64,28 @@ struct Slot {
   tsgne_graph* g = nullptr;
   float* state = nullptr;  // Y, U, gains: float32[3][n][2]
   int32_t* t = nullptr;
+  int32_t id = -1;         // index of this slot's pause limit in the round's limit array (kept while active)
   int32_t progress = 0;    // steps already run (host view)
 };
 
-// Tile rows of a request when the server does not fix them: graphs with
-// enough tiles to fill the GPU by themselves (kLargeRequest nodes: 128 blocks
-// of 1024), and every request of a server that runs one at a time, take the
-// single-graph plan's choice; smaller ones sharing rounds take 8, whose tiles
-// keep a shared round's steps short.
-constexpr int32_t kLargeRequest = 131072;
-int32_t request_tile_rows(int32_t n, int32_t max_active) {
-  return (n >= kLargeRequest || max_active == 1) ? make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R : 8;
+// Tile rows of a request when the server does not fix them: the single-graph
+// plan's choice, whose step is the shortest for the request's size (1 or 2
+// rows for the smallest graphs, whose steps are a few microseconds, up to
+// 14-16 for those that fill the GPU by themselves).  The layout therefore
+// equals the request's own tsgne_run with the automatic tile.
+int32_t request_tile_rows(int32_t n) { return make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R; }
+
+// Distinct tile sizes, hence the most batched groups a round can hold.
+constexpr int kMaxGroups = 8;
+
+// Shortest time of one step of the smallest graphs (a few dependent kernel
+// launches), below which a step does not get faster however few pairs it has.
+constexpr double kStepFloorSeconds = 15e-6;
+
+// Estimated GPU time of n_iter steps of an n-node graph alone.
+double alone_seconds(int32_t n, int32_t n_iter, double pair_rate) {
+  const double pairs = (double)n * (double)(n - 1);
+  return (double)n_iter * std::max(pairs / pair_rate, kStepFloorSeconds);
 }
 
 // Device bytes a request holds while active (graph, workspace, state) plus the
@@ -99,6 +115,8 @@ struct tsgne_server {
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> all;
   std::vector<Slot> active;
+  std::vector<Slot> incoming;      // admitted during a round; active from the next one
+  std::vector<int32_t> free_ids;   // limit-array indices not held by a slot
   bool stop = false;
   int32_t n_active = 0;  // active.size(), published under mu for other threads
   uint64_t next_ticket = 1;
@@ -108,7 +126,13 @@ struct tsgne_server {
   std::vector<double> latencies_ms;
   bool have_first = false;
   Clock::time_point t_first, t_last_done;
-  double busy_s = 0.0;
+  double busy_s = 0.0, admit_s = 0.0, plan_s = 0.0;
+  // ordered pairs evaluated per second, refined from measured rounds
+  double pair_rate = 5e12;
+  // the one-at-a-time schedule's clock: the estimated finish of the last
+  // request admitted, had every request run alone in submission order
+  Clock::time_point fifo_clock;
+  bool fifo_started = false;
 
   void run();
   void admit(hipStream_t s);
@@ -130,22 +154,15 @@ tsgne_status build_slot(const Request& r, int32_t R, hipStream_t s, Slot& out) {
   const std::vector<int32_t>& rp = r.row_ptr;
   const std::vector<int32_t>& col = r.col;
   const int64_t nnz = r.nnz;
-  int32_t* d_rp = nullptr;
-  int32_t* d_col = nullptr;
-  float* d_X = nullptr;
-  struct Tmp {
-    int32_t*& a;
-    int32_t*& b;
-    float*& c;
-    ~Tmp() {
-      dfree(a);
-      dfree(b);
-      dfree(c);
-    }
-  } tmp{d_rp, d_col, d_X};
-  TSGNE_HIP(dalloc(&d_rp, rp.size()), "allocate request CSR");
-  TSGNE_HIP(dalloc(&d_col, (size_t)std::max<int64_t>(nnz, 1)), "allocate request CSR");
-  TSGNE_HIP(dalloc(&d_X, (size_t)r.n * r.d), "allocate request embedding");
+  // uploads in stream-ordered pool memory, released once the graph is built
+  ScratchBlock tmp;
+  tmp.s = s;
+  const size_t b_rp = (sizeof(int32_t) * rp.size() + 255) & ~(size_t)255;
+  const size_t b_col = (sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1) + 255) & ~(size_t)255;
+  TSGNE_HIP(scratch_alloc(&tmp.p, b_rp + b_col + sizeof(float) * r.X.size(), s), "allocate request uploads");
+  int32_t* d_rp = static_cast<int32_t*>(tmp.p);
+  int32_t* d_col = reinterpret_cast<int32_t*>(static_cast<char*>(tmp.p) + b_rp);
+  float* d_X = reinterpret_cast<float*>(static_cast<char*>(tmp.p) + b_rp + b_col);
   TSGNE_HIP(hipMemcpyAsync(d_rp, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice, s), "upload CSR");
   if (nnz) TSGNE_HIP(hipMemcpyAsync(d_col, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s), "upload CSR");
   TSGNE_HIP(hipMemcpyAsync(d_X, r.X.data(), sizeof(float) * r.X.size(), hipMemcpyHostToDevice, s), "upload X");
@@ -197,6 +214,8 @@ void tsgne_server::finish(Slot& sl, tsgne_status st, const std::string& why, boo
     }
   }
   free_slot(sl);
+  if (sl.id >= 0) free_ids.push_back(sl.id);
+  sl.id = -1;
   std::lock_guard<std::mutex> lk(mu);
   hbm_used -= r.footprint;
   r.t_done = Clock::now();
@@ -216,71 +235,116 @@ void tsgne_server::finish(Slot& sl, tsgne_status st, const std::string& why, boo
 }
 
 void tsgne_server::admit(hipStream_t s) {
+  const Clock::time_point t0 = Clock::now();
   for (;;) {
     std::shared_ptr<Request> r;
     {
       std::lock_guard<std::mutex> lk(mu);
-      if (queue.empty() || (int32_t)active.size() >= cfg.max_active) return;  // only this thread changes active
-      if (hbm_used + queue.front()->footprint > (size_t)cfg.hbm_budget) return;  // wait for memory
+      // only this thread changes active and incoming
+      if (queue.empty() || (int32_t)(active.size() + incoming.size()) >= cfg.max_active || free_ids.empty()) break;
+      if (hbm_used + queue.front()->footprint > (size_t)cfg.hbm_budget) break;  // wait for memory
       r = queue.front();
       queue.pop_front();
       hbm_used += r->footprint;
       r->t_admit = Clock::now();
       r->admitted = true;
     }
+    // its finish in the one-at-a-time schedule: after the previous request's
+    // and its own estimated time alone
+    const Clock::time_point start = (!fifo_started || r->t_submit > fifo_clock) ? r->t_submit : fifo_clock;
+    r->fifo_due = start + std::chrono::duration_cast<Clock::duration>(
+                              std::chrono::duration<double>(alone_seconds(r->n, r->n_iter, pair_rate)));
+    fifo_clock = r->fifo_due;
+    fifo_started = true;
     Slot sl;
     sl.req = r;
+    sl.id = free_ids.back();
+    free_ids.pop_back();
     tsgne_status st = build_slot(*r, r->R, s, sl);
     if (st != TSGNE_OK) {
       finish(sl, st, tsgne_last_error(), false, s);
       continue;
     }
-    active.push_back(sl);
+    incoming.push_back(sl);
   }
+  std::lock_guard<std::mutex> lk(mu);
+  admit_s += seconds_since(t0, Clock::now());
 }
+
+namespace {
+
+// Steps of one captured chunk of a group (replayed as often as a round needs).
+constexpr int32_t kChunkSteps = 64;
+
+// The active requests of one tile size: their batched plan, the members'
+// tickets in plan order, and the captured chunks of that plan by length.
+struct Group {
+  BatchRun run;
+  std::vector<uint64_t> tickets;
+  std::map<int32_t, hipGraphExec_t> chunks;
+  ~Group() { clear(); }
+  void clear() {
+    for (auto& kv : chunks) (void)hipGraphExecDestroy(kv.second);
+    chunks.clear();
+  }
+};
+
+// A captured chunk of `len` batched steps of a group's plan.
+tsgne_status chunk_exec(Group& gr, int32_t len, const tsgne_params& p, hipStream_t cap, hipGraphExec_t* out) {
+  auto it = gr.chunks.find(len);
+  if (it != gr.chunks.end()) {
+    *out = it->second;
+    return TSGNE_OK;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  TSGNE_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t le = hipSuccess;
+  for (int32_t k = 0; k < len && le == hipSuccess; ++k) le = launch_batch_step(gr.run.plan(), p, cap);
+  hipError_t e = hipStreamEndCapture(cap, &graph);
+  if (e == hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "capture a serving chunk");
+  gr.chunks[len] = exec;
+  *out = exec;
+  return TSGNE_OK;
+}
+
+}  // namespace
 
 void tsgne_server::run() {
   (void)hipSetDevice(device);
-  hipStream_t s = nullptr;
-  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-  int32_t* limits = nullptr;  // per-member pause step of the current round
+  hipStream_t s = nullptr, s_build = nullptr, cap = nullptr;
+  bool streams_ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+                    hipStreamCreateWithFlags(&s_build, hipStreamNonBlocking) == hipSuccess &&
+                    hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+  for (int32_t k = cfg.max_active - 1; k >= 0; --k) free_ids.push_back(k);
+  int32_t* limits = nullptr;  // per-slot pause step of the current round, indexed by slot id
   if (dalloc(&limits, (size_t)cfg.max_active) != hipSuccess) limits = nullptr;
+  std::vector<int32_t> lim_host((size_t)cfg.max_active, 0);
   // Requests are grouped by tile size, one batched plan per group.  With
   // several groups a round forks one branch per group (its own stream) from
   // the main stream and joins them at the end, so the groups run together.
-  std::map<int32_t, BatchRun> groups;
-  bool plan_valid = false;
-  constexpr int kMaxGroups = 6;  // the supported tile sizes
+  std::map<int32_t, Group> groups;
   hipStream_t branch[kMaxGroups] = {};
   hipEvent_t fork = nullptr, join[kMaxGroups] = {};
   bool branches_ok = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; k < kMaxGroups && branches_ok; ++k)
     branches_ok = hipStreamCreateWithFlags(&branch[k], hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&join[k], hipEventDisableTiming) == hipSuccess;
-  // Captured rounds for the current membership, keyed by the number of steps
-  // each group's branch launches (groups in ascending tile size).
-  std::map<std::vector<int32_t>, hipGraphExec_t> execs;
-  constexpr size_t kMaxExecs = 32;
-  auto clear_execs = [&]() {
-    for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
-    execs.clear();
-  };
-  auto drop_execs = [&]() {
-    clear_execs();
-    plan_valid = false;
-  };
-  // ordered pairs evaluated per second, refined from measured rounds
-  double pair_rate = 5e12;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty() || !incoming.empty(); });
       if (stop) break;
     }
-    const size_t before = active.size();
-    admit(s);
+    // requests admitted during the last round join now; when nothing runs,
+    // admission happens here
+    if (active.empty() && incoming.empty()) admit(s_build);
+    for (Slot& sl : incoming) active.push_back(sl);
+    incoming.clear();
     // cancelled active requests leave at a round boundary
-    bool changed = active.size() != before;
     for (size_t k = 0; k < active.size();) {
       bool c;
       {
@@ -290,41 +354,53 @@ void tsgne_server::run() {
       if (c) {
         finish(active[k], TSGNE_E_CANCELLED, "cancelled", false, s);
         active.erase(active.begin() + (long)k);
-        changed = true;
       } else {
         ++k;
       }
     }
-    if (changed) drop_execs();
     {
       std::lock_guard<std::mutex> lk(mu);
       n_active = (int32_t)active.size();
     }
     if (active.empty()) continue;
-    const Clock::time_point t0 = Clock::now();
-    tsgne_status st = limits ? TSGNE_OK : fail(TSGNE_E_NOMEM, "allocate round limits");
-    if (st == TSGNE_OK && !plan_valid) {
-      std::map<int32_t, std::vector<BatchMember>> members;
-      for (size_t k = 0; k < active.size(); ++k) {
-        Slot& sl = active[k];
-        const size_t len = 2 * (size_t)sl.req->n;
-        members[sl.req->R].push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t,
-                                                 limits + k, sl.req->n_iter});
+    const Clock::time_point t_plan = Clock::now();
+    tsgne_status st = (limits && streams_ok) ? TSGNE_OK : fail(TSGNE_E_NOMEM, "allocate server state");
+    // Re-plan the groups whose membership changed (the others keep their
+    // plans and captured chunks).
+    if (st == TSGNE_OK) {
+      std::map<int32_t, std::vector<size_t>> by_tile;
+      for (size_t k = 0; k < active.size(); ++k) by_tile[active[k].req->R].push_back(k);
+      if (by_tile.size() > (size_t)kMaxGroups) st = fail(TSGNE_E_INVAL, "more tile sizes than round branches");
+      if (by_tile.size() > 1 && !branches_ok) st = fail(TSGNE_E_DEVICE, "create round branches");
+      for (auto it = groups.begin(); it != groups.end();) {
+        if (!by_tile.count(it->first)) it = groups.erase(it);
+        else ++it;
       }
-      groups.clear();
-      if (members.size() > 1 && !branches_ok) st = fail(TSGNE_E_DEVICE, "create round branches");
-      for (auto& kv : members) {
+      for (auto& kv : by_tile) {
         if (st != TSGNE_OK) break;
-        st = groups[kv.first].setup(kv.second.data(), (int32_t)kv.second.size(), kv.first, &cfg.params);
+        std::vector<uint64_t> tickets;
+        for (size_t k : kv.second) tickets.push_back(active[k].req->ticket);
+        Group& gr = groups[kv.first];
+        if (gr.tickets == tickets) continue;
+        gr.clear();
+        gr.tickets.clear();
+        std::vector<BatchMember> members;
+        for (size_t k : kv.second) {
+          Slot& sl = active[k];
+          const size_t len = 2 * (size_t)sl.req->n;
+          members.push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t,
+                                        limits + sl.id, sl.req->n_iter});
+        }
+        st = gr.run.setup(members.data(), (int32_t)members.size(), kv.first, &cfg.params);
+        if (st == TSGNE_OK) gr.tickets = tickets;
       }
-      if (st == TSGNE_OK) plan_valid = true;
     }
     // Steps per request this round: an equal share of the round's target time
     // (small graphs take many steps, large ones few), or the same count for
     // all when no target is set.
     // With oldest_share > 0 the request that has waited longest gets that
     // fraction of the round and the others split the rest.
-    std::vector<int32_t> take(active.size()), lim(active.size());
+    std::vector<int32_t> take(active.size());
     std::map<int32_t, int32_t> longest;  // per group (tile size): the most steps any member takes
     double pairs = 0.0;
     const double budget = cfg.round_ms > 0.f ? pair_rate * 1e-3 * cfg.round_ms : 0.0;
@@ -333,19 +409,75 @@ void tsgne_server::run() {
       if (active[k].req->t_submit < active[oldest].req->t_submit) oldest = k;
     const bool favour = cfg.oldest_share > 0.f && active.size() > 1;
     auto per_step_of = [&](size_t k) { return (double)active[k].req->n * (double)(active[k].req->n - 1) + 1.0; };
-    // Smallest-first: the time left after the oldest request's part goes to
-    // the requests with the least remaining work, each as much as a round
-    // allows, until it runs out (the others still take one step).
+    auto remaining = [&](size_t k) { return per_step_of(k) * (double)(active[k].req->n_iter - active[k].progress); };
     std::vector<double> share_of(active.size(), 0.0);
-    if (cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST && budget > 0.0) {
+    // Short-first: requests with at most long_ms of GPU time left are short;
+    // they take what they need first, least remaining first.  Long requests
+    // run one at a time in submission order (the oldest, the head, takes the
+    // rest of the round; the others are paused), so a long request never
+    // shares the GPU with another long one.  While a head runs, the short
+    // requests take at most short_share of a round, and only out of the
+    // head's slack: the time by which it is ahead of its finish in the
+    // one-at-a-time schedule (fifo_due), after the work of every active
+    // request due before it (short requests due before it take what they
+    // need).  So short requests overtake a long one only as far as it would
+    // otherwise have waited for them, and no request is meant to finish later
+    // than it would one at a time.
+    std::vector<char> paused(active.size(), 0);
+    if (cfg.rest_policy == TSGNE_SHARE_SHORT_FIRST && budget > 0.0) {
+      const double long_pairs = pair_rate * 1e-3 * (double)cfg.long_ms;
+      std::vector<size_t> shorts;
+      size_t head = active.size();
+      for (size_t k = 0; k < active.size(); ++k) {
+        if (remaining(k) <= long_pairs) {
+          shorts.push_back(k);
+        } else if (head == active.size() || active[k].req->t_submit < active[head].req->t_submit) {
+          head = k;
+        }
+      }
+      for (size_t k = 0; k < active.size(); ++k)
+        if (k != head && remaining(k) > long_pairs) paused[k] = 1;
+      std::stable_sort(shorts.begin(), shorts.end(), [&](size_t a, size_t b) { return remaining(a) < remaining(b); });
+      double left = budget;
+      if (head < active.size()) {
+        // seconds of GPU work due no later than the head, the head's own included
+        double ahead = 0.0;
+        for (size_t k = 0; k < active.size(); ++k)
+          if (active[k].req->fifo_due <= active[head].req->fifo_due)
+            ahead += alone_seconds(active[k].req->n, active[k].req->n_iter - active[k].progress, pair_rate);
+        const double slack = std::chrono::duration<double>(active[head].req->fifo_due - Clock::now()).count() -
+                             ahead - 1e-3 * (double)cfg.round_ms;
+        left = std::min(budget * (double)cfg.short_share, std::max(0.0, slack) * pair_rate);
+      }
+      double used = 0.0;
+      for (size_t k : shorts) {
+        const double want =
+            per_step_of(k) * (double)std::min(cfg.steps_per_round, active[k].req->n_iter - active[k].progress);
+        // a short request due before the head is ahead of it in the
+        // one-at-a-time order too: it takes what it needs
+        const bool ahead_of_head = head < active.size() && active[k].req->fifo_due <= active[head].req->fifo_due;
+        const double give = ahead_of_head ? want : std::min(want, left);
+        if (give < per_step_of(k)) {  // no room for one step this round
+          paused[k] = 1;
+          continue;
+        }
+        share_of[k] = give;
+        if (!ahead_of_head) left -= give;
+        used += give;
+      }
+      if (head < active.size()) share_of[head] = std::max(budget - used, budget * (1.0 - (double)cfg.short_share));
+    } else if (cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST && budget > 0.0) {
+      // Smallest-first: the time left after the oldest request's part goes to
+      // the requests with the least remaining work, each as much as a round
+      // allows, until it runs out (the others still take one step).
       std::vector<size_t> rest;
       for (size_t k = 0; k < active.size(); ++k)
         if (!(favour && k == oldest)) rest.push_back(k);
-      auto remaining = [&](size_t k) { return per_step_of(k) * (double)(active[k].req->n_iter - active[k].progress); };
       std::stable_sort(rest.begin(), rest.end(), [&](size_t a, size_t b) { return remaining(a) < remaining(b); });
       double left = favour ? budget * (1.0 - cfg.oldest_share) : budget;
       for (size_t k : rest) {
-        const double want = per_step_of(k) * (double)std::min(cfg.steps_per_round, active[k].req->n_iter - active[k].progress);
+        const double want =
+            per_step_of(k) * (double)std::min(cfg.steps_per_round, active[k].req->n_iter - active[k].progress);
         share_of[k] = std::min(want, left);
         left -= share_of[k];
       }
@@ -354,63 +486,82 @@ void tsgne_server::run() {
     for (size_t k = 0; k < active.size(); ++k) {
       const Slot& sl = active[k];
       const double per_step = per_step_of(k);
-      const double share = cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST ? share_of[k]
+      const bool by_share =
+          cfg.rest_policy == TSGNE_SHARE_SMALLEST_FIRST || cfg.rest_policy == TSGNE_SHARE_SHORT_FIRST;
+      const double share = by_share ? share_of[k]
                            : !favour ? budget / (double)active.size()
                            : k == oldest ? budget * cfg.oldest_share
                                          : budget * (1.0 - cfg.oldest_share) / (double)(active.size() - 1);
       int32_t steps = cfg.steps_per_round;
-      if (budget > 0.0) steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
+      if (budget > 0.0)
+        steps = (int32_t)std::max(1.0, std::min((double)cfg.steps_per_round, std::floor(share / per_step)));
+      if (paused[k]) steps = 0;
       steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
       take[k] = steps;
-      lim[k] = sl.progress + steps;
-      int32_t& most = longest[sl.req->R];
-      most = std::max(most, steps);
-      pairs += per_step * steps;
     }
-    // Each group's branch launches the power of two at or above its own
-    // longest allotment (members pause at their limit on the device), so a
-    // group of large graphs that take one step in a round does not launch
-    // the many steps a group of small ones takes beside it.
-    std::vector<int32_t> lens;
-    for (const auto& kv : groups) {
+    // a round always advances someone: if every request was paused (no long
+    // request, and no short one with room for a step), the one with the least
+    // remaining work takes one step
+    if (std::all_of(take.begin(), take.end(), [](int32_t v) { return v == 0; })) {
+      size_t k0 = 0;
+      for (size_t k = 1; k < active.size(); ++k)
+        if (remaining(k) < remaining(k0)) k0 = k;
+      take[k0] = std::min(1, active[k0].req->n_iter - active[k0].progress);
+    }
+    for (size_t k = 0; k < active.size(); ++k) {
+      const Slot& sl = active[k];
+      lim_host[(size_t)sl.id] = sl.progress + take[k];
+      int32_t& most = longest[sl.req->R];
+      most = std::max(most, take[k]);
+      pairs += per_step_of(k) * take[k];
+    }
+    // Each group replays a captured chunk of its own length (the power of two
+    // at or above its longest allotment, at most kChunkSteps) as often as that
+    // allotment needs; members pause at their limit on the device, so a group
+    // of large graphs that take one step in a round does not launch the many
+    // steps a group of small ones takes beside it.
+    struct Launch {
+      hipGraphExec_t exec;
+      int32_t reps;
+    };
+    std::vector<Launch> launches;
+    for (auto& kv : groups) {
+      if (st != TSGNE_OK) break;
+      const int32_t most = longest[kv.first];
+      if (most <= 0) continue;  // every member pauses: nothing to launch
       int32_t len = 1;
-      while (len < longest[kv.first]) len *= 2;
-      lens.push_back(std::min(len, cfg.steps_per_round));
+      while (len < most && len < kChunkSteps) len *= 2;
+      hipGraphExec_t exec = nullptr;
+      st = chunk_exec(kv.second, len, cfg.params, cap, &exec);
+      launches.push_back(Launch{exec, (most + len - 1) / len});
     }
     if (st == TSGNE_OK) {
-      hipError_t e = hipMemcpyAsync(limits, lim.data(), sizeof(int32_t) * lim.size(), hipMemcpyHostToDevice, s);
+      hipError_t e = hipMemcpyAsync(limits, lim_host.data(), sizeof(int32_t) * lim_host.size(),
+                                    hipMemcpyHostToDevice, s);
       if (e != hipSuccess) st = hip_fail(e, "upload round limits");
     }
-    if (st == TSGNE_OK && !execs.count(lens)) {
-      if (execs.size() >= kMaxExecs) clear_execs();
-      hipGraph_t graph = nullptr;
-      hipGraphExec_t exec = nullptr;
-      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-      hipError_t le = hipSuccess;
-      if (groups.size() == 1) {
-        const BatchRun& br = groups.begin()->second;
-        for (int32_t k = 0; e == hipSuccess && k < lens[0] && le == hipSuccess; ++k)
-          le = launch_batch_step(br.plan(), cfg.params, s);
-      } else if (e == hipSuccess) {
-        le = hipEventRecord(fork, s);
-        int gi = 0;
-        for (auto it = groups.begin(); it != groups.end() && le == hipSuccess; ++it, ++gi) {
-          le = hipStreamWaitEvent(branch[gi], fork, 0);
-          for (int32_t k = 0; k < lens[gi] && le == hipSuccess; ++k)
-            le = launch_batch_step(it->second.plan(), cfg.params, branch[gi]);
-          if (le == hipSuccess) le = hipEventRecord(join[gi], branch[gi]);
-        }
-        for (int k = 0; k < gi && le == hipSuccess; ++k) le = hipStreamWaitEvent(s, join[k], 0);
-      }
-      if (e == hipSuccess) e = hipStreamEndCapture(s, &graph);
-      if (e == hipSuccess) e = le;
-      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (graph) (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) st = hip_fail(e, "capture a serving round");
-      else execs[lens] = exec;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      plan_s += seconds_since(t_plan, Clock::now());
     }
+    const Clock::time_point t0 = Clock::now();
     if (st == TSGNE_OK) {
-      hipError_t e = hipGraphLaunch(execs[lens], s);
+      hipError_t e = hipSuccess;
+      if (launches.size() == 1) {
+        for (int32_t r = 0; r < launches[0].reps && e == hipSuccess; ++r) e = hipGraphLaunch(launches[0].exec, s);
+      } else {
+        e = hipEventRecord(fork, s);
+        for (size_t gi = 0; gi < launches.size() && e == hipSuccess; ++gi) {
+          e = hipStreamWaitEvent(branch[gi], fork, 0);
+          for (int32_t r = 0; r < launches[gi].reps && e == hipSuccess; ++r)
+            e = hipGraphLaunch(launches[gi].exec, branch[gi]);
+          if (e == hipSuccess) e = hipEventRecord(join[gi], branch[gi]);
+          if (e == hipSuccess) e = hipStreamWaitEvent(s, join[gi], 0);
+        }
+      }
+      // queued requests are admitted (their affinities built on their own
+      // stream) while the round runs; they join the next round
+      if (e == hipSuccess) admit(s_build);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = hip_fail(e, "run a serving round");
     }
@@ -419,7 +570,7 @@ void tsgne_server::run() {
       const std::string why = tsgne_last_error();
       for (Slot& sl : active) finish(sl, st, why, false, s);
       active.clear();
-      drop_execs();
+      groups.clear();
       continue;
     }
     const double dt = seconds_since(t0, Clock::now());
@@ -429,30 +580,29 @@ void tsgne_server::run() {
       ++rounds;
       busy_s += dt;
     }
-    bool left = false;
     for (size_t k = 0, j = 0; k < active.size(); ++j) {
       Slot& sl = active[k];
       sl.progress += take[j];
       if (sl.progress >= sl.req->n_iter) {
         finish(sl, TSGNE_OK, "", true, s);
         active.erase(active.begin() + (long)k);
-        left = true;
       } else {
         ++k;
       }
     }
-    if (left) drop_execs();
     {
       std::lock_guard<std::mutex> lk(mu);
       n_active = (int32_t)active.size();
     }
   }
-  drop_execs();
-  for (Slot& sl : active) {
-    sl.req->cancel = true;
-    finish(sl, TSGNE_E_CANCELLED, "server destroyed", false, s);
+  groups.clear();
+  for (std::vector<Slot>* v : {&active, &incoming}) {
+    for (Slot& sl : *v) {
+      sl.req->cancel = true;
+      finish(sl, TSGNE_E_CANCELLED, "server destroyed", false, s);
+    }
+    v->clear();
   }
-  active.clear();
   {
     std::lock_guard<std::mutex> lk(mu);
     for (auto& r : queue) {
@@ -465,14 +615,14 @@ void tsgne_server::run() {
     n_active = 0;
     cv_done.notify_all();
   }
-  groups.clear();
   dfree(limits);
   for (int k = 0; k < kMaxGroups; ++k) {
     if (branch[k]) (void)hipStreamDestroy(branch[k]);
     if (join[k]) (void)hipEventDestroy(join[k]);
   }
   if (fork) (void)hipEventDestroy(fork);
-  if (s) (void)hipStreamDestroy(s);
+  for (hipStream_t q : {s, s_build, cap})
+    if (q) (void)hipStreamDestroy(q);
 }
 
 extern "C" {
@@ -482,12 +632,14 @@ void tsgne_server_config_default(tsgne_server_config* c) {
   c->hbm_budget = 0;
   c->max_active = 64;
   c->max_queue = 1 << 20;
-  c->steps_per_round = 64;
+  c->steps_per_round = 512;
   c->round_ms = 25.0f;
   c->oldest_share = 0.5f;
-  c->rest_policy = TSGNE_SHARE_EQUAL;
+  c->rest_policy = TSGNE_SHARE_SHORT_FIRST;
   c->tile_rows = 0;
   tsgne_params_default(&c->params);
+  c->long_ms = 150.0f;
+  c->short_share = 0.3f;
 }
 
 tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** out) {
@@ -497,8 +649,12 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
   if (!std::isfinite(cfg->round_ms)) return fail(TSGNE_E_INVAL, "round_ms must be finite");
   if (!(cfg->oldest_share >= 0.f && cfg->oldest_share < 1.f))
     return fail(TSGNE_E_INVAL, "oldest_share must lie in [0, 1)");
-  if (cfg->rest_policy != TSGNE_SHARE_EQUAL && cfg->rest_policy != TSGNE_SHARE_SMALLEST_FIRST)
-    return fail(TSGNE_E_INVAL, "rest_policy must be TSGNE_SHARE_EQUAL or TSGNE_SHARE_SMALLEST_FIRST");
+  if (cfg->rest_policy != TSGNE_SHARE_EQUAL && cfg->rest_policy != TSGNE_SHARE_SMALLEST_FIRST &&
+      cfg->rest_policy != TSGNE_SHARE_SHORT_FIRST)
+    return fail(TSGNE_E_INVAL, "rest_policy must be TSGNE_SHARE_EQUAL, _SMALLEST_FIRST or _SHORT_FIRST");
+  if (!(cfg->long_ms >= 0.f) || !std::isfinite(cfg->long_ms)) return fail(TSGNE_E_INVAL, "long_ms must be >= 0");
+  if (!(cfg->short_share > 0.f && cfg->short_share < 1.f))
+    return fail(TSGNE_E_INVAL, "short_share must lie in (0, 1)");
   if (cfg->max_active < 1 || cfg->max_queue < 1 || cfg->steps_per_round < 1)
     return fail(TSGNE_E_INVAL, "max_active, max_queue and steps_per_round must be >= 1");
   if (cfg->tile_rows != 0 && !tile_rows_supported(cfg->tile_rows))
@@ -534,7 +690,7 @@ tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uin
   r->d = rq->d;
   r->n_iter = rq->n_iter;
   r->perplexity = rq->perplexity;
-  r->R = srv->cfg.tile_rows ? srv->cfg.tile_rows : request_tile_rows(rq->n, srv->cfg.max_active);
+  r->R = srv->cfg.tile_rows ? srv->cfg.tile_rows : request_tile_rows(rq->n);
   r->footprint = footprint_bytes(rq->n, rq->m, rq->d, r->R);
   if (r->footprint > (size_t)srv->cfg.hbm_budget)
     return fail(TSGNE_E_NOMEM, "request needs more device memory than the server's budget");
@@ -651,6 +807,8 @@ tsgne_status tsgne_server_get_stats(tsgne_server* srv, tsgne_server_stats* out) 
   out->hbm_budget = srv->cfg.hbm_budget;
   out->rounds = srv->rounds;
   out->busy_s = srv->busy_s;
+  out->admit_s = srv->admit_s;
+  out->plan_s = srv->plan_s;
   std::vector<double> l = srv->latencies_ms;
   std::sort(l.begin(), l.end());
   auto pct = [&](double q) {

@@ -272,11 +272,10 @@ def batch_workload(count: int = 256, seed: int | None = None, n_min: int = 500, 
     return out
 
 
-def serving_requests(count: int, seed: int | None = None, n_min: int = 1_000, n_max: int = 200_000) -> list[GraphInput]:
-    """Layout requests: node counts log-uniform in [n_min, n_max], average degree
-    uniform in [2, 8], half plain SBM (4-40 equal communities, mixing 0.18) and
-    half DC-SBM (power law 2.5, 4-40 log-normal communities), embeddings of 64
-    or 128 dimensions (half each)."""
+def serving_request_specs(count: int, seed: int | None = None, n_min: int = 1_000,
+                          n_max: int = 200_000) -> list[tuple]:
+    """The drawn parameters of each request of a serving stream, in order:
+    (index, n, average degree, communities, d, SBM or DC-SBM, seed base)."""
     s = MASTER_SEED + 5 if seed is None else seed
     rng = _rng(s, 10)
     out = []
@@ -285,13 +284,28 @@ def serving_requests(count: int, seed: int | None = None, n_min: int = 1_000, n_
         avg = float(rng.uniform(2.0, 8.0))
         comm = int(rng.integers(4, 41))
         d = 64 if rng.random() < 0.5 else 128
-        if rng.random() < 0.5:
-            edges, labels = sbm_sparse(n, comm, avg, 0.18, s * 1000 + k)
-        else:
-            edges, labels = dcsbm(n, int(round(n * avg / 2)), 2.5, comm, 0.18, s * 1000 + k)
-        X = embedding(labels, d, 0.5, s * 1000 + k)
-        out.append(GraphInput(n, edges, labels, X, initial_layout(n, s * 1000 + k), "req%d" % k))
+        plain = bool(rng.random() < 0.5)
+        out.append((k, n, avg, comm, d, plain, s))
     return out
+
+
+def serving_request(spec: tuple) -> GraphInput:
+    """One request of a serving stream from its drawn parameters."""
+    k, n, avg, comm, d, plain, s = spec
+    if plain:
+        edges, labels = sbm_sparse(n, comm, avg, 0.18, s * 1000 + k)
+    else:
+        edges, labels = dcsbm(n, int(round(n * avg / 2)), 2.5, comm, 0.18, s * 1000 + k)
+    X = embedding(labels, d, 0.5, s * 1000 + k)
+    return GraphInput(n, edges, labels, X, initial_layout(n, s * 1000 + k), "req%d" % k)
+
+
+def serving_requests(count: int, seed: int | None = None, n_min: int = 1_000, n_max: int = 200_000) -> list[GraphInput]:
+    """Layout requests: node counts log-uniform in [n_min, n_max], average degree
+    uniform in [2, 8], half plain SBM (4-40 equal communities, mixing 0.18) and
+    half DC-SBM (power law 2.5, 4-40 log-normal communities), embeddings of 64
+    or 128 dimensions (half each)."""
+    return [serving_request(spec) for spec in serving_request_specs(count, seed, n_min, n_max)]
 
 
 def small_sbm(n: int, n_comm: int, avg_deg: float, d: int, seed: int, mu: float = 0.18) -> GraphInput:

@@ -36,6 +36,7 @@ AUTOTUNE_TILES = (4, 8, 12, 16)   # the autotuner's candidates, in its output or
 
 TSGNE_SHARE_EQUAL = 0
 TSGNE_SHARE_SMALLEST_FIRST = 1
+TSGNE_SHARE_SHORT_FIRST = 2
 
 # every symbol include/tsgne.h declares
 EXPORTED = (
@@ -89,6 +90,8 @@ class tsgne_server_config(ctypes.Structure):
         ("round_ms", ctypes.c_float),
         ("oldest_share", ctypes.c_float),
         ("rest_policy", ctypes.c_int32),
+        ("long_ms", ctypes.c_float),
+        ("short_share", ctypes.c_float),
     ]
 
 
@@ -110,7 +113,8 @@ class tsgne_server_stats(ctypes.Structure):
         ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
         ("cancelled", ctypes.c_int64), ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
         ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64), ("rounds", ctypes.c_int64),
-        ("busy_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+        ("busy_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("plan_s", ctypes.c_double),
+        ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
         ("latency_mean_ms", ctypes.c_double), ("layouts_per_s", ctypes.c_double),
     ]
 
@@ -617,7 +621,8 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
                  steps_per_round: int = 64, tile_rows: int = 0, params: tsgne_params | None = None,
-                 round_ms: float = 25.0, oldest_share: float | None = None, rest_policy: int | None = None):
+                 round_ms: float = 25.0, oldest_share: float | None = None, rest_policy: int | None = None,
+                 long_ms: float | None = None, short_share: float | None = None):
         cfg = tsgne_server_config()
         lib().tsgne_server_config_default(ctypes.byref(cfg))
         cfg.hbm_budget = int(hbm_budget)
@@ -630,6 +635,10 @@ class Server:
             cfg.oldest_share = float(oldest_share)
         if rest_policy is not None:
             cfg.rest_policy = int(rest_policy)
+        if long_ms is not None:
+            cfg.long_ms = float(long_ms)
+        if short_share is not None:
+            cfg.short_share = float(short_share)
         if params is not None:
             cfg.params = params
         h = ctypes.c_void_p(None)

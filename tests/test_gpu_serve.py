@@ -34,14 +34,19 @@ def requests(seed):
     return gis, iters
 
 
-EQ, SF = tsgne.TSGNE_SHARE_EQUAL, tsgne.TSGNE_SHARE_SMALLEST_FIRST
+EQ, SF, SH = tsgne.TSGNE_SHARE_EQUAL, tsgne.TSGNE_SHARE_SMALLEST_FIRST, tsgne.TSGNE_SHARE_SHORT_FIRST
 
 
-@pytest.mark.parametrize("max_active,budget_scale,round_ms,oldest,policy", [
-    (3, 0, 25.0, 0.5, EQ), (64, 1.3, 25.0, 0.5, EQ), (64, 0, 0.0, 0.5, EQ), (64, 0, 0.05, 0.5, EQ),
-    (64, 0, 0.05, 0.0, EQ), (64, 0, 0.05, 0.9, EQ), (64, 0, 0.05, 0.5, SF), (64, 0, 0.05, 0.0, SF),
-    (3, 1.3, 0.05, 0.5, SF)])
-def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, policy):
+# long_ms (short-first policy): 150 ms makes every request here short, 0 makes
+# every one long (one at a time in submission order, the others paused), and
+# 2e-3 ms splits them.
+@pytest.mark.parametrize("max_active,budget_scale,round_ms,oldest,policy,long_ms", [
+    (3, 0, 25.0, 0.5, EQ, 150), (64, 1.3, 25.0, 0.5, EQ, 150), (64, 0, 0.0, 0.5, EQ, 150),
+    (64, 0, 0.05, 0.5, EQ, 150), (64, 0, 0.05, 0.0, EQ, 150), (64, 0, 0.05, 0.9, EQ, 150),
+    (64, 0, 0.05, 0.5, SF, 150), (64, 0, 0.05, 0.0, SF, 150), (3, 1.3, 0.05, 0.5, SF, 150),
+    (64, 0, 0.05, 0.5, SH, 150), (64, 0, 0.05, 0.5, SH, 0.0), (64, 0, 0.05, 0.5, SH, 2e-3),
+    (3, 1.3, 0.05, 0.5, SH, 2e-3), (64, 0, 25.0, 0.5, SH, 2e-3)])
+def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, policy, long_ms):
     gis, iters = requests(1)
     budget = 0
     if budget_scale:
@@ -51,7 +56,7 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, polic
         budget = int(budget_scale * (8 * nb * nb * 64 * R + 2100 * 400 + 40 * 2100 * 6))
     srv = tsgne.Server(hbm_budget=budget, max_active=max_active, steps_per_round=7, tile_rows=4,
                        params=tsgne.tsgne_params_default(**PARAMS), round_ms=round_ms, oldest_share=oldest,
-                       rest_policy=policy)
+                       rest_policy=policy, long_ms=long_ms)
     tickets = [srv.submit(gi.n, gi.edges, gi.X, gi.Y0, 30.0, k) for gi, k in zip(gis, iters)]
     outs = [srv.wait(t) for t in tickets]
     st = srv.stats()
@@ -74,10 +79,11 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, polic
 
 
 def test_per_request_tiles_mix_equals_alone(gpu):
-    # tile_rows = 0: small requests take 8 rows and the 145000- and
-    # 152000-node requests the single-graph plan's choices (14 and 16 with the
-    # current cost model), so a round runs three batched plans on parallel
-    # branches; each layout still equals its own run alone.
+    # tile_rows = 0: every request takes the single-graph plan's choice (1
+    # row per lane for 400-2100 nodes, 14 and 16 for the 145000- and
+    # 152000-node requests with the current cost model), so a round runs
+    # three batched plans on parallel branches; each layout still equals its
+    # own run alone with the automatic tile.
     gis = [synth.small_sbm(n, 3, 5.0, 8, 300 + k) for k, n in enumerate([900, 2100, 400])]
     gis += [synth.small_sbm(n, 6, 6.0, 8, 310 + k) for k, n in enumerate([145_000, 152_000])]
     iters = [40, 25, 60, 12, 9]
@@ -90,7 +96,7 @@ def test_per_request_tiles_mix_equals_alone(gpu):
     assert st["completed"] == len(gis) and st["failed"] == 0
     for gi, k, (status, Y) in zip(gis, iters, outs):
         assert status == tsgne.TSGNE_OK
-        assert np.array_equal(Y, alone(gi, k, 8 if gi.n < 131072 else 0, gpu)), gi.n
+        assert np.array_equal(Y, alone(gi, k, 0, gpu)), gi.n
 
 
 def test_one_at_a_time_takes_the_single_graph_plan(gpu):
@@ -144,9 +150,17 @@ def test_server_config_rejects(gpu):
         with pytest.raises(tsgne.TsgneError) as e:
             tsgne.Server(oldest_share=bad)
         assert e.value.status == tsgne.TSGNE_E_INVAL
-    for bad in (2, -1):
+    for bad in (3, -1):
         with pytest.raises(tsgne.TsgneError) as e:
             tsgne.Server(rest_policy=bad)
+        assert e.value.status == tsgne.TSGNE_E_INVAL
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(tsgne.TsgneError) as e:
+            tsgne.Server(long_ms=bad)
+        assert e.value.status == tsgne.TSGNE_E_INVAL
+    for bad in (0.0, 1.0, float("nan")):
+        with pytest.raises(tsgne.TsgneError) as e:
+            tsgne.Server(short_share=bad)
         assert e.value.status == tsgne.TSGNE_E_INVAL
 
 
@@ -195,7 +209,7 @@ def test_full_serving_stream_sampled(gpu):
     order = sorted(range(len(reqs)), key=lambda k: reqs[k].n)
     for k in (order[0], order[len(order) // 2], order[-1]):
         gi = reqs[k]
-        R = 8 if gi.n < 131072 else 0
+        R = 0   # the single-graph plan's tile, as the server gives every request
         import torch
         rp, col = T.tsgne_csr_from_edges(gi.n, gi.edges)
         g = T.tsgne_build_P(torch.from_numpy(rp).to(gpu), torch.from_numpy(col).to(gpu),
