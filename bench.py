@@ -251,10 +251,10 @@ def poisson_arrivals(count, qps, seed=2310_11186):
     return np.cumsum(rng.exponential(1.0 / qps, size=count))
 
 
-def serve_kwargs(n_iter, tile_rows=0):
+def serve_kwargs(n_iter, tile_rows=0, round_ms=25.0):
     from paper_2310_11186_amd import tsgne
     params = tsgne.tsgne_params_default(exaggeration_iters=n_iter // 4)
-    return dict(max_active=64, steps_per_round=512, round_ms=25.0, tile_rows=tile_rows, params=params)
+    return dict(max_active=64, steps_per_round=512, round_ms=round_ms, tile_rows=tile_rows, params=params)
 
 
 def serving_leg(reqs, n_iter):
@@ -302,7 +302,7 @@ def run_serve(args) -> int:
     n_iter = args.n_iter if args.n_iter is not None else 500
     specs = synth.serving_request_specs(count)
     sizes = [sp[1] for sp in specs]
-    kw = serve_kwargs(n_iter, args.tile_rows)
+    kw = serve_kwargs(n_iter, args.tile_rows, args.serve_round_ms)
     kw1 = dict(kw, max_active=1)
     kw_old = dict(kw, rest_policy=tsgne.TSGNE_SHARE_EQUAL, oldest_share=0.5)
     configs = {"batched": kw, "one_at_a_time": kw1, "oldest_share": kw_old}
@@ -324,12 +324,18 @@ def run_serve(args) -> int:
         st_sat, wall_sat = serve_stream(kw, specs, [0.0] * count, n_iter, pool, label="saturated")
         sat_rate = count / wall_sat
         log("saturated: %.2f layouts/s" % sat_rate)
-        result["saturated"] = {"layouts_per_s": sat_rate, "seconds": wall_sat}
+        result["saturated"] = {"layouts_per_s": sat_rate, "seconds": wall_sat,
+                               "batched": stream_summary(st_sat, wall_sat, count)}
         if not args.serve_only:
             st_sat1, wall_sat1 = serve_stream(kw1, specs, [0.0] * count, n_iter, pool, label="saturated, one")
             log("saturated, one at a time: %.2f layouts/s" % (count / wall_sat1))
             result["saturated"].update(one_at_a_time_layouts_per_s=count / wall_sat1,
-                                       speedup_vs_one_at_a_time=wall_sat1 / wall_sat)
+                                       speedup_vs_one_at_a_time=wall_sat1 / wall_sat,
+                                       one_at_a_time=stream_summary(st_sat1, wall_sat1, count))
+        if args.serve_saturated_only:
+            pool.close()
+            print(json.dumps(result), flush=True)
+            return 0
         qps = 0.8 * sat_rate
     arrivals = poisson_arrivals(count, qps)
     result["config"]["qps"] = qps
@@ -710,6 +716,8 @@ def main() -> int:
                     help="serve: Poisson arrival rate (req/s); skips the saturated runs")
     ap.add_argument("--serve-only", default="", choices=["", "batched", "one_at_a_time", "oldest_share"],
                     help="serve: run only this configuration at the Poisson rate")
+    ap.add_argument("--serve-round-ms", type=float, default=25.0, help="serve: the server's round_ms")
+    ap.add_argument("--serve-saturated-only", action="store_true", help="serve: only the saturated runs")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="default workload: requests in the serving leg (0 = skip it)")
     ap.add_argument("--shards", type=int, default=8, help="shard: GPUs the repulsion is split over")

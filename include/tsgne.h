@@ -573,6 +573,11 @@ TSGNE_API tsgne_status tsgne_server_wait(tsgne_server* srv, uint64_t ticket, flo
  * queued).  E_INVAL for an unknown ticket, E_BUSY while queued or running. */
 TSGNE_API tsgne_status tsgne_server_latency(tsgne_server* srv, uint64_t ticket, double* latency_ms, double* queued_ms);
 
+/* The error message of a finished request that failed (empty if it
+ * succeeded), copied into buf (at most len - 1 characters and a NUL).
+ * E_INVAL for an unknown ticket, E_BUSY while queued or running. */
+TSGNE_API tsgne_status tsgne_server_error(tsgne_server* srv, uint64_t ticket, char* buf, int32_t len);
+
 /* Forgets a finished request (its layout copy is released).  E_BUSY if running. */
 TSGNE_API tsgne_status tsgne_server_release(tsgne_server* srv, uint64_t ticket);
 

@@ -75,8 +75,11 @@ struct Slot {
 // equals the request's own tsgne_run with the automatic tile.
 int32_t request_tile_rows(int32_t n) { return make_plan(n, 0, TSGNE_REPULSION_SYMMETRIC).R; }
 
-// Distinct tile sizes, hence the most batched groups a round can hold.
+// Distinct tile sizes, hence the most batched groups of short requests a
+// round can hold (the running long request's group comes on top).
 constexpr int kMaxGroups = 8;
+// Group key of the running long request: kHeadKey + its tile rows.
+constexpr int32_t kHeadKey = 1000;
 
 // Shortest time of one step of the smallest graphs (a few dependent kernel
 // launches), below which a step does not get faster however few pairs it has.
@@ -109,14 +112,20 @@ using namespace tsgne;
 struct tsgne_server {
   tsgne_server_config cfg{};
   int device = 0;
-  std::thread worker;
+  std::thread worker, admitter;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  // Held while the worker captures a chunk and while the admitter builds a
+  // request: a build's synchronous HIP calls (hipMalloc, hipMemcpy on the null
+  // stream) must not run while a stream is being captured.
+  std::mutex capture_mu;
+  std::condition_variable cv_work, cv_done, cv_admit;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> all;
   std::vector<Slot> active;
-  std::vector<Slot> incoming;      // admitted during a round; active from the next one
+  std::vector<Slot> incoming;      // built by the admitter; active from the next round
   std::vector<int32_t> free_ids;   // limit-array indices not held by a slot
+  int32_t building = 0;            // requests the admitter is building
+  bool admitter_done = false;      // the admitter has left its loop (it touches incoming no more)
   bool stop = false;
   int32_t n_active = 0;  // active.size(), published under mu for other threads
   uint64_t next_ticket = 1;
@@ -135,7 +144,8 @@ struct tsgne_server {
   bool fifo_started = false;
 
   void run();
-  void admit(hipStream_t s);
+  void admit_loop();
+  bool can_admit() const;
   void finish(Slot& sl, tsgne_status st, const std::string& why, bool copy_out, hipStream_t s);
 };
 
@@ -214,10 +224,11 @@ void tsgne_server::finish(Slot& sl, tsgne_status st, const std::string& why, boo
     }
   }
   free_slot(sl);
+  std::lock_guard<std::mutex> lk(mu);
   if (sl.id >= 0) free_ids.push_back(sl.id);
   sl.id = -1;
-  std::lock_guard<std::mutex> lk(mu);
   hbm_used -= r.footprint;
+  cv_admit.notify_one();
   r.t_done = Clock::now();
   r.status = st;
   r.error = why;
@@ -234,41 +245,65 @@ void tsgne_server::finish(Slot& sl, tsgne_status st, const std::string& why, boo
   cv_done.notify_all();
 }
 
-void tsgne_server::admit(hipStream_t s) {
-  const Clock::time_point t0 = Clock::now();
+// Under mu: the next queued request can be admitted (a slot and its memory).
+bool tsgne_server::can_admit() const {
+  if (queue.empty() || free_ids.empty()) return false;
+  if (n_active + (int32_t)incoming.size() + building >= cfg.max_active) return false;
+  return hbm_used + queue.front()->footprint <= (size_t)cfg.hbm_budget;  // else wait for memory
+}
+
+// The admitter thread: takes queued requests in submission order as slots and
+// memory allow, uploads them and builds their affinities on a stream of its
+// own (overlapping the rounds the worker runs), and hands the built slots to
+// the worker, which adds them at its next round boundary.
+void tsgne_server::admit_loop() {
+  (void)hipSetDevice(device);
+  hipStream_t s = nullptr;
+  const bool stream_ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
   for (;;) {
     std::shared_ptr<Request> r;
+    Slot sl;
     {
-      std::lock_guard<std::mutex> lk(mu);
-      // only this thread changes active and incoming
-      if (queue.empty() || (int32_t)(active.size() + incoming.size()) >= cfg.max_active || free_ids.empty()) break;
-      if (hbm_used + queue.front()->footprint > (size_t)cfg.hbm_budget) break;  // wait for memory
+      std::unique_lock<std::mutex> lk(mu);
+      cv_admit.wait(lk, [&] { return stop || can_admit(); });
+      if (stop) break;
       r = queue.front();
       queue.pop_front();
       hbm_used += r->footprint;
       r->t_admit = Clock::now();
       r->admitted = true;
+      // its finish in the one-at-a-time schedule: after the previous
+      // request's and its own estimated time alone
+      const Clock::time_point start = (!fifo_started || r->t_submit > fifo_clock) ? r->t_submit : fifo_clock;
+      r->fifo_due = start + std::chrono::duration_cast<Clock::duration>(
+                                std::chrono::duration<double>(alone_seconds(r->n, r->n_iter, pair_rate)));
+      fifo_clock = r->fifo_due;
+      fifo_started = true;
+      sl.req = r;
+      sl.id = free_ids.back();
+      free_ids.pop_back();
+      building = 1;
     }
-    // its finish in the one-at-a-time schedule: after the previous request's
-    // and its own estimated time alone
-    const Clock::time_point start = (!fifo_started || r->t_submit > fifo_clock) ? r->t_submit : fifo_clock;
-    r->fifo_due = start + std::chrono::duration_cast<Clock::duration>(
-                              std::chrono::duration<double>(alone_seconds(r->n, r->n_iter, pair_rate)));
-    fifo_clock = r->fifo_due;
-    fifo_started = true;
-    Slot sl;
-    sl.req = r;
-    sl.id = free_ids.back();
-    free_ids.pop_back();
-    tsgne_status st = build_slot(*r, r->R, s, sl);
-    if (st != TSGNE_OK) {
-      finish(sl, st, tsgne_last_error(), false, s);
-      continue;
+    const Clock::time_point t0 = Clock::now();
+    tsgne_status st;
+    {
+      std::lock_guard<std::mutex> cl(capture_mu);
+      st = stream_ok ? build_slot(*r, r->R, s, sl) : fail(TSGNE_E_DEVICE, "create the admission stream");
     }
-    incoming.push_back(sl);
+    const std::string why = st == TSGNE_OK ? std::string() : std::string(tsgne_last_error());
+    if (st != TSGNE_OK) finish(sl, st, why, false, s);
+    std::lock_guard<std::mutex> lk(mu);
+    building = 0;
+    admit_s += seconds_since(t0, Clock::now());
+    if (st == TSGNE_OK) {
+      incoming.push_back(sl);
+      cv_work.notify_one();
+    }
   }
+  if (s) (void)hipStreamDestroy(s);
   std::lock_guard<std::mutex> lk(mu);
-  admit_s += seconds_since(t0, Clock::now());
+  admitter_done = true;
+  cv_work.notify_all();
 }
 
 namespace {
@@ -315,11 +350,9 @@ tsgne_status chunk_exec(Group& gr, int32_t len, const tsgne_params& p, hipStream
 
 void tsgne_server::run() {
   (void)hipSetDevice(device);
-  hipStream_t s = nullptr, s_build = nullptr, cap = nullptr;
+  hipStream_t s = nullptr, cap = nullptr;
   bool streams_ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
-                    hipStreamCreateWithFlags(&s_build, hipStreamNonBlocking) == hipSuccess &&
                     hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
-  for (int32_t k = cfg.max_active - 1; k >= 0; --k) free_ids.push_back(k);
   int32_t* limits = nullptr;  // per-slot pause step of the current round, indexed by slot id
   if (dalloc(&limits, (size_t)cfg.max_active) != hipSuccess) limits = nullptr;
   std::vector<int32_t> lim_host((size_t)cfg.max_active, 0);
@@ -336,14 +369,14 @@ void tsgne_server::run() {
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty() || !incoming.empty(); });
+      cv_work.wait(lk, [&] { return stop || !active.empty() || !incoming.empty(); });
       if (stop) break;
+      // requests the admitter built during the last round join now
+      for (Slot& sl : incoming) active.push_back(sl);
+      incoming.clear();
+      n_active = (int32_t)active.size();
+      cv_admit.notify_one();  // slots may have come free
     }
-    // requests admitted during the last round join now; when nothing runs,
-    // admission happens here
-    if (active.empty() && incoming.empty()) admit(s_build);
-    for (Slot& sl : incoming) active.push_back(sl);
-    incoming.clear();
     // cancelled active requests leave at a round boundary
     for (size_t k = 0; k < active.size();) {
       bool c;
@@ -361,40 +394,11 @@ void tsgne_server::run() {
     {
       std::lock_guard<std::mutex> lk(mu);
       n_active = (int32_t)active.size();
+      cv_admit.notify_one();  // slots may have come free
     }
     if (active.empty()) continue;
     const Clock::time_point t_plan = Clock::now();
     tsgne_status st = (limits && streams_ok) ? TSGNE_OK : fail(TSGNE_E_NOMEM, "allocate server state");
-    // Re-plan the groups whose membership changed (the others keep their
-    // plans and captured chunks).
-    if (st == TSGNE_OK) {
-      std::map<int32_t, std::vector<size_t>> by_tile;
-      for (size_t k = 0; k < active.size(); ++k) by_tile[active[k].req->R].push_back(k);
-      if (by_tile.size() > (size_t)kMaxGroups) st = fail(TSGNE_E_INVAL, "more tile sizes than round branches");
-      if (by_tile.size() > 1 && !branches_ok) st = fail(TSGNE_E_DEVICE, "create round branches");
-      for (auto it = groups.begin(); it != groups.end();) {
-        if (!by_tile.count(it->first)) it = groups.erase(it);
-        else ++it;
-      }
-      for (auto& kv : by_tile) {
-        if (st != TSGNE_OK) break;
-        std::vector<uint64_t> tickets;
-        for (size_t k : kv.second) tickets.push_back(active[k].req->ticket);
-        Group& gr = groups[kv.first];
-        if (gr.tickets == tickets) continue;
-        gr.clear();
-        gr.tickets.clear();
-        std::vector<BatchMember> members;
-        for (size_t k : kv.second) {
-          Slot& sl = active[k];
-          const size_t len = 2 * (size_t)sl.req->n;
-          members.push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t,
-                                        limits + sl.id, sl.req->n_iter});
-        }
-        st = gr.run.setup(members.data(), (int32_t)members.size(), kv.first, &cfg.params);
-        if (st == TSGNE_OK) gr.tickets = tickets;
-      }
-    }
     // Steps per request this round: an equal share of the round's target time
     // (small graphs take many steps, large ones few), or the same count for
     // all when no target is set.
@@ -424,10 +428,11 @@ void tsgne_server::run() {
     // otherwise have waited for them, and no request is meant to finish later
     // than it would one at a time.
     std::vector<char> paused(active.size(), 0);
-    if (cfg.rest_policy == TSGNE_SHARE_SHORT_FIRST && budget > 0.0) {
-      const double long_pairs = pair_rate * 1e-3 * (double)cfg.long_ms;
+    size_t head = active.size();  // the running long request (short-first), if any
+    const double long_pairs = pair_rate * 1e-3 * (double)cfg.long_ms;
+    const bool short_first = cfg.rest_policy == TSGNE_SHARE_SHORT_FIRST && budget > 0.0;
+    if (short_first) {
       std::vector<size_t> shorts;
-      size_t head = active.size();
       for (size_t k = 0; k < active.size(); ++k) {
         if (remaining(k) <= long_pairs) {
           shorts.push_back(k);
@@ -499,30 +504,80 @@ void tsgne_server::run() {
       steps = std::max(0, std::min(steps, sl.req->n_iter - sl.progress));
       take[k] = steps;
     }
+    // Batched groups: one per tile size; under short-first the running long
+    // request has a group of its own (run after the others, see below) and
+    // the paused long requests are in none, so that no launch carries the
+    // tiles of graphs that wait.
+    std::vector<int32_t> key(active.size());
+    for (size_t k = 0; k < active.size(); ++k) {
+      const int32_t R = active[k].req->R;
+      key[k] = !short_first ? R : k == head ? kHeadKey + R : remaining(k) > long_pairs ? -1 : R;
+    }
     // a round always advances someone: if every request was paused (no long
     // request, and no short one with room for a step), the one with the least
     // remaining work takes one step
     if (std::all_of(take.begin(), take.end(), [](int32_t v) { return v == 0; })) {
-      size_t k0 = 0;
-      for (size_t k = 1; k < active.size(); ++k)
-        if (remaining(k) < remaining(k0)) k0 = k;
-      take[k0] = std::min(1, active[k0].req->n_iter - active[k0].progress);
+      size_t k0 = active.size();
+      for (size_t k = 0; k < active.size(); ++k)
+        if (key[k] >= 0 && (k0 == active.size() || remaining(k) < remaining(k0))) k0 = k;
+      if (k0 < active.size()) take[k0] = std::min(1, active[k0].req->n_iter - active[k0].progress);
     }
     for (size_t k = 0; k < active.size(); ++k) {
       const Slot& sl = active[k];
+      if (key[k] < 0) take[k] = 0;
       lim_host[(size_t)sl.id] = sl.progress + take[k];
-      int32_t& most = longest[sl.req->R];
-      most = std::max(most, take[k]);
+      if (key[k] >= 0) {
+        int32_t& most = longest[key[k]];
+        most = std::max(most, take[k]);
+      }
       pairs += per_step_of(k) * take[k];
     }
+    // Re-plan the groups whose membership changed (the others keep their
+    // plans and captured chunks).
+    if (st == TSGNE_OK) {
+      std::map<int32_t, std::vector<size_t>> by_tile;
+      for (size_t k = 0; k < active.size(); ++k)
+        if (key[k] >= 0) by_tile[key[k]].push_back(k);
+      if (by_tile.size() > (size_t)kMaxGroups + 1) st = fail(TSGNE_E_INVAL, "more tile sizes than round branches");
+      if (by_tile.size() > 1 && !branches_ok) st = fail(TSGNE_E_DEVICE, "create round branches");
+      for (auto it = groups.begin(); it != groups.end();) {
+        if (!by_tile.count(it->first)) it = groups.erase(it);
+        else ++it;
+      }
+      for (auto& kv : by_tile) {
+        if (st != TSGNE_OK) break;
+        std::vector<uint64_t> tickets;
+        for (size_t k : kv.second) tickets.push_back(active[k].req->ticket);
+        Group& gr = groups[kv.first];
+        if (gr.tickets == tickets) continue;
+        gr.clear();
+        gr.tickets.clear();
+        std::vector<BatchMember> members;
+        for (size_t k : kv.second) {
+          Slot& sl = active[k];
+          const size_t len = 2 * (size_t)sl.req->n;
+          members.push_back(BatchMember{sl.g, sl.state, sl.state + len, sl.state + 2 * len, sl.t,
+                                        limits + sl.id, sl.req->n_iter});
+        }
+        st = gr.run.setup(members.data(), (int32_t)members.size(), kv.first % kHeadKey, &cfg.params);
+        if (st == TSGNE_OK) gr.tickets = tickets;
+      }
+    }
+
     // Each group replays a captured chunk of its own length (the power of two
     // at or above its longest allotment, at most kChunkSteps) as often as that
     // allotment needs; members pause at their limit on the device, so a group
     // of large graphs that take one step in a round does not launch the many
     // steps a group of small ones takes beside it.
+    // The groups run together, except the running long request's group,
+    // which runs after them: the long request fills the GPU by itself, and
+    // small graphs' steps beside its kernels cost it more than they gain;
+    // the small requests, batched together, take about the time one of them
+    // takes alone.
     struct Launch {
       hipGraphExec_t exec;
       int32_t reps;
+      bool after;
     };
     std::vector<Launch> launches;
     for (auto& kv : groups) {
@@ -532,8 +587,11 @@ void tsgne_server::run() {
       int32_t len = 1;
       while (len < most && len < kChunkSteps) len *= 2;
       hipGraphExec_t exec = nullptr;
-      st = chunk_exec(kv.second, len, cfg.params, cap, &exec);
-      launches.push_back(Launch{exec, (most + len - 1) / len});
+      {
+        std::lock_guard<std::mutex> cl(capture_mu);
+        st = chunk_exec(kv.second, len, cfg.params, cap, &exec);
+      }
+      launches.push_back(Launch{exec, (most + len - 1) / len, kv.first >= kHeadKey});
     }
     if (st == TSGNE_OK) {
       hipError_t e = hipMemcpyAsync(limits, lim_host.data(), sizeof(int32_t) * lim_host.size(),
@@ -547,21 +605,22 @@ void tsgne_server::run() {
     const Clock::time_point t0 = Clock::now();
     if (st == TSGNE_OK) {
       hipError_t e = hipSuccess;
-      if (launches.size() == 1) {
-        for (int32_t r = 0; r < launches[0].reps && e == hipSuccess; ++r) e = hipGraphLaunch(launches[0].exec, s);
-      } else {
+      std::vector<const Launch*> together, after;
+      for (const Launch& l : launches) (l.after ? after : together).push_back(&l);
+      if (together.size() == 1) {
+        for (int32_t r = 0; r < together[0]->reps && e == hipSuccess; ++r) e = hipGraphLaunch(together[0]->exec, s);
+      } else if (together.size() > 1) {
         e = hipEventRecord(fork, s);
-        for (size_t gi = 0; gi < launches.size() && e == hipSuccess; ++gi) {
+        for (size_t gi = 0; gi < together.size() && e == hipSuccess; ++gi) {
           e = hipStreamWaitEvent(branch[gi], fork, 0);
-          for (int32_t r = 0; r < launches[gi].reps && e == hipSuccess; ++r)
-            e = hipGraphLaunch(launches[gi].exec, branch[gi]);
+          for (int32_t r = 0; r < together[gi]->reps && e == hipSuccess; ++r)
+            e = hipGraphLaunch(together[gi]->exec, branch[gi]);
           if (e == hipSuccess) e = hipEventRecord(join[gi], branch[gi]);
           if (e == hipSuccess) e = hipStreamWaitEvent(s, join[gi], 0);
         }
       }
-      // queued requests are admitted (their affinities built on their own
-      // stream) while the round runs; they join the next round
-      if (e == hipSuccess) admit(s_build);
+      for (const Launch* l : after)
+        for (int32_t r = 0; r < l->reps && e == hipSuccess; ++r) e = hipGraphLaunch(l->exec, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) st = hip_fail(e, "run a serving round");
     }
@@ -574,9 +633,9 @@ void tsgne_server::run() {
       continue;
     }
     const double dt = seconds_since(t0, Clock::now());
-    if (dt > 0.0 && pairs > 1e9) pair_rate = 0.5 * pair_rate + 0.5 * pairs / dt;
     {
       std::lock_guard<std::mutex> lk(mu);
+      if (dt > 0.0 && pairs > 1e9) pair_rate = 0.5 * pair_rate + 0.5 * pairs / dt;
       ++rounds;
       busy_s += dt;
     }
@@ -593,9 +652,15 @@ void tsgne_server::run() {
     {
       std::lock_guard<std::mutex> lk(mu);
       n_active = (int32_t)active.size();
+      cv_admit.notify_one();  // slots may have come free
     }
   }
   groups.clear();
+  {
+    // wait for the admitter to leave its loop: nothing else touches these then
+    std::unique_lock<std::mutex> lk(mu);
+    cv_work.wait(lk, [&] { return admitter_done; });
+  }
   for (std::vector<Slot>* v : {&active, &incoming}) {
     for (Slot& sl : *v) {
       sl.req->cancel = true;
@@ -621,7 +686,7 @@ void tsgne_server::run() {
     if (join[k]) (void)hipEventDestroy(join[k]);
   }
   if (fork) (void)hipEventDestroy(fork);
-  for (hipStream_t q : {s, s_build, cap})
+  for (hipStream_t q : {s, cap})
     if (q) (void)hipStreamDestroy(q);
 }
 
@@ -674,7 +739,9 @@ tsgne_status tsgne_server_create(const tsgne_server_config* cfg, tsgne_server** 
     }
     srv->cfg.hbm_budget = (int64_t)(0.8 * (double)free_b);
   }
+  for (int32_t k = srv->cfg.max_active - 1; k >= 0; --k) srv->free_ids.push_back(k);
   srv->worker = std::thread([srv] { srv->run(); });
+  srv->admitter = std::thread([srv] { srv->admit_loop(); });
   *out = srv;
   return TSGNE_OK;
 }
@@ -719,7 +786,7 @@ tsgne_status tsgne_server_submit(tsgne_server* srv, const tsgne_request* rq, uin
   srv->all[r->ticket] = r;
   ++srv->submitted;
   *ticket = r->ticket;
-  srv->cv_work.notify_one();
+  srv->cv_admit.notify_one();
   return TSGNE_OK;
 }
 
@@ -758,6 +825,19 @@ tsgne_status tsgne_server_latency(tsgne_server* srv, uint64_t ticket, double* la
   if (!r.done) return fail(TSGNE_E_BUSY, "request still queued or running");
   if (latency_ms) *latency_ms = 1e3 * seconds_since(r.t_submit, r.t_done);
   if (queued_ms) *queued_ms = 1e3 * seconds_since(r.t_submit, r.admitted ? r.t_admit : r.t_done);
+  return TSGNE_OK;
+}
+
+tsgne_status tsgne_server_error(tsgne_server* srv, uint64_t ticket, char* buf, int32_t len) {
+  if (!srv || !buf || len < 1) return fail(TSGNE_E_INVAL, "null pointer or empty buffer");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(TSGNE_E_INVAL, "unknown ticket");
+  const Request& r = *it->second;
+  if (!r.done) return fail(TSGNE_E_BUSY, "request still queued or running");
+  const size_t n = std::min(r.error.size(), (size_t)len - 1);
+  std::copy(r.error.begin(), r.error.begin() + (long)n, buf);
+  buf[n] = 0;
   return TSGNE_OK;
 }
 
@@ -832,7 +912,10 @@ tsgne_status tsgne_server_destroy(tsgne_server* srv) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stop = true;
     srv->cv_work.notify_all();
+    srv->cv_admit.notify_all();
   }
+  // the admitter first: once it has stopped, only the worker holds slots
+  if (srv->admitter.joinable()) srv->admitter.join();
   if (srv->worker.joinable()) srv->worker.join();
   delete srv;
   return TSGNE_OK;

@@ -46,7 +46,7 @@ EXPORTED = (
     "tsgne_graph_from_host_P", "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
     "tsgne_kl", "tsgne_kl_noalloc", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
-    "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
+    "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_error", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
     "tsgne_server_destroy", "tsgne_shard_create", "tsgne_shard_info", "tsgne_shard_repulsion", "tsgne_shard_set_timing",
     "tsgne_shard_timing", "tsgne_shard_free",
 )
@@ -171,6 +171,7 @@ def lib():
             "tsgne_server_wait": (st, [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32)]),
             "tsgne_server_latency": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
+            "tsgne_server_error": (st, [vp, ctypes.c_uint64, ctypes.c_char_p, i32]),
             "tsgne_server_release": (st, [vp, ctypes.c_uint64]),
             "tsgne_server_cancel": (st, [vp, ctypes.c_uint64]),
             "tsgne_server_get_stats": (st, [vp, ctypes.POINTER(tsgne_server_stats)]),
@@ -681,6 +682,12 @@ class Server:
         lat, q = ctypes.c_double(0.0), ctypes.c_double(0.0)
         _check(lib().tsgne_server_latency(self._h, ticket, ctypes.byref(lat), ctypes.byref(q)))
         return lat.value, q.value
+
+    def error(self, ticket: int) -> str:
+        """The error message of a finished request ('' if it succeeded)."""
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib().tsgne_server_error(self._h, ticket, buf, len(buf)))
+        return buf.value.decode()
 
     def cancel(self, ticket: int) -> None:
         _check(lib().tsgne_server_cancel(self._h, ticket))

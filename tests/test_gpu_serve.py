@@ -61,8 +61,10 @@ def test_mix_equals_alone(gpu, max_active, budget_scale, round_ms, oldest, polic
     outs = [srv.wait(t) for t in tickets]
     st = srv.stats()
     times = [srv.latency(t) for t in tickets]
+    errors = [srv.error(t) for t in tickets]
     srv.close()
-    assert st["completed"] == len(gis) and st["failed"] == 0
+    assert st["completed"] == len(gis) and st["failed"] == 0, ([o[0] for o in outs], errors)
+    assert errors == [""] * len(gis)
     assert st["latency_p99_ms"] >= st["latency_p50_ms"] > 0 and st["layouts_per_s"] > 0
     # per-request times: queued <= latency; the nearest-rank percentiles and the
     # mean of the per-request latencies are the server's statistics
