@@ -100,10 +100,13 @@ def test_precision_split_vs_fp32(gpu):
 C3_STATES = (0, 1, 10, 125, 250, 500, 1000)
 C3_ITERS, C3_TEE = 1000, 250
 # Bars on the final KL of the 1000-iteration snowball layouts relative to the
-# oracle's (the spread of the oracle's own runs under a 1e-7 perturbation of
-# Y0 is the measure of what rounding alone does to it).
-C3_KL_BAR_SPLIT = 0.05
-C3_KL_BAR_FP32 = 0.08
+# oracle's.  The layout is a chaotic function of rounding in the early phase:
+# the FP64 oracle itself, started from Y0 perturbed by 1e-7 relative (five
+# seeds), ends at -0.25 %, +0.22 %, -0.32 %, +0.07 % and +0.18 % of its
+# unperturbed run's final KL (4.7682); the bars are about three times the
+# widest of those (measured on the GPU: split -0.02 %, all-FP32 +0.30 %).
+C3_KL_BAR_SPLIT = 0.01
+C3_KL_BAR_FP32 = 0.01
 
 
 def shadow_step(g, gpu, p, t, s, orp, ocol, oP, eta, early_exaggeration=12.0):
