@@ -13,7 +13,9 @@ value = pair interactions per second over the whole job
 Prints one JSON line (rank 0).  Also reports the roofline of the dominant
 kernel (the repulsion, timed with HIP events on its own stream; the layouts
 of the timed region run with phase timing on, so each step's launches are
-issued one by one between events), the FP64 oracle timed on the host cores
+issued one by one between events; for layouts under 2 s, the time of a
+layout without phase timing, whose steps replay captured chunks, is reported
+beside it as layout_ms_replayed), the FP64 oracle timed on the host cores
 over a bounded sample, and, for the default workload, a compact serving leg
 (48 requests of 1K-200K nodes, 500 iterations each: saturated and Poisson
 arrivals at 0.8x the saturated rate, continuous batching against one request
@@ -130,21 +132,48 @@ def run_batch(args) -> int:
     Y0 = [torch.from_numpy(gi.Y0).to(dev) for gi in gis]
     params = tsgne.tsgne_params_default(exaggeration_iters=t_ee)
     best, ms = tsgne.tsgne_autotune(graphs, Y0, params, steps=3)
-    log("autotuner: ms/step for tile_rows %s = %s -> %d" % (tsgne.AUTOTUNE_TILES, ["%.2f" % m for m in ms], best))
-    params_b = tsgne.tsgne_params_default(exaggeration_iters=t_ee, tile_rows=best)
+    log("autotuner (one tile): ms/step for tile_rows %s = %s -> %d" %
+        (tsgne.AUTOTUNE_TILES, ["%.2f" % m for m in ms], best))
+    t_tune = time.perf_counter()
+    tiles, ms_uniform, ms_tuned = tsgne.tsgne_autotune_tiles(graphs, Y0, params, steps=3)
+    tune_s = time.perf_counter() - t_tune
+    by_bucket = {}
+    for gi, t in zip(gis, tiles):
+        by_bucket[int(math.floor(math.log2(gi.n)))] = t
+    log("autotuner (tile per size bucket, %.1f s): %s, %.2f -> %.2f ms/step" %
+        (tune_s, by_bucket, ms_uniform, ms_tuned))
+    params_b = tsgne.tsgne_params_default(exaggeration_iters=t_ee, repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC)
+    params_u = tsgne.tsgne_params_default(exaggeration_iters=t_ee, tile_rows=best)
     pairs = sum(float(gi.n) * (gi.n - 1) for gi in gis) * n_iter
 
+    def padded_pairs(rows_of):
+        tot = 0.0
+        for gi, R in zip(gis, rows_of):
+            T = 64 * R
+            nb = (gi.n + T - 1) // T
+            tot += float(nb * T) ** 2
+        return tot
+
+    padding = {"tuned": padded_pairs(tiles) / (pairs / n_iter) - 1.0,
+               "one_tile": padded_pairs([best] * len(gis)) / (pairs / n_iter) - 1.0}
+
     Yb = [y.clone() for y in Y0]
-    tsgne.tsgne_batch_run(graphs[:8], Yb[:8], [5] * 8, params_b)        # warm-up of the batched path
-    Yb = [y.clone() for y in Y0]
+    tsgne.tsgne_batch_run_tiles(graphs[:8], Yb[:8], [5] * 8, tiles[:8], params_b)   # warm-up of the batched path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         Yb = [y.clone() for y in Y0]
-        tsgne.tsgne_batch_run(graphs, Yb, [n_iter] * len(graphs), params_b)
+        tsgne.tsgne_batch_run_tiles(graphs, Yb, [n_iter] * len(graphs), tiles, params_b)
     torch.cuda.synchronize()
     batched_s = (time.perf_counter() - t0) / args.steps
-    log("batched: %.2f s per 256 layouts" % batched_s)
+    log("batched, tuned tiles: %.2f s per 256 layouts" % batched_s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Yb = [y.clone() for y in Y0]
+    tsgne.tsgne_batch_run(graphs, Yb, [n_iter] * len(graphs), params_u)
+    torch.cuda.synchronize()
+    uniform_s = time.perf_counter() - t0
+    log("batched, one tile (%d): %.2f s" % (best, uniform_s))
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -163,8 +192,12 @@ def run_batch(args) -> int:
         "data": "synthetic",
         "config": {"workload": "batch256", "graphs": len(gis), "nodes_total": int(sum(gi.n for gi in gis)),
                    "sum_n2": float(sum(float(gi.n) ** 2 for gi in gis)), "n_iter": n_iter, "d": 64,
-                   "tile_rows": best, "autotune_ms_per_step": ms, "build_P_s": build_s},
+                   "tile_rows_by_size_bucket": by_bucket, "autotune_s": tune_s,
+                   "autotune_ms_per_step": {"one_tile": ms_uniform, "tuned": ms_tuned},
+                   "padding_of_pair_work": padding, "build_P_s": build_s},
         "layouts_per_s": len(gis) / batched_s,
+        "one_tile": {"tile_rows": best, "seconds": uniform_s, "autotune_ms_per_step": ms,
+                     "pair_interactions_per_s": pairs / uniform_s},
         "one_at_a_time": {"seconds": seq_s, "pair_interactions_per_s": pairs / seq_s,
                           "layouts_per_s": len(gis) / seq_s},
         "speedup_vs_one_at_a_time": seq_s / batched_s,
@@ -819,6 +852,20 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
+    # The timed layouts launch each step's kernels one by one between events
+    # (phase timing); a layout without timing replays captured chunks of
+    # steps.  For layouts short enough that launches matter, time that too.
+    replayed_ms = None
+    if elapsed / args.steps < 2.0:
+        reps = 5
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            one_step()
+        torch.cuda.synchronize()
+        replayed_ms = (time.perf_counter() - t1) / reps * 1e3
+        log("layout without phase timing (captured replay): %.2f ms" % replayed_ms)
+
     n = gi.n
     pairs_per_iter = n * (n - 1)
     value = args.steps * n_iter * pairs_per_iter / elapsed
@@ -882,6 +929,7 @@ def main() -> int:
             "launches": rep_launches,
         },
         "phase_avg_ms": phase_avg_ms,
+        "layout_ms_replayed": replayed_ms,
         "final_kl": kls[-1] if kls else None,
         "quality": quality,
     }

@@ -468,6 +468,42 @@ TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* c
                                       const tsgne_params* p, int32_t steps, int32_t* best_tile_rows,
                                       double* ms_per_step, void* stream);
 
+/*
+ * tsgne_batch_run with a repulsion tile per graph: tile_rows[k] (1, 2, 4, 8,
+ * 12, 14, 15, 16; 0 = the single-graph plan's choice for graph k's size).
+ * The graphs of each tile size form one batched plan; the plans run side by
+ * side (one branch stream each, forked and joined inside each captured chunk
+ * of steps).  Graph k's layout equals tsgne_run of it alone with tile_rows[k]
+ * and the symmetric repulsion, bit for bit.  Arguments, errors and
+ * synchronisation as tsgne_batch_run.
+ */
+TSGNE_API tsgne_status tsgne_batch_run_tiles(tsgne_graph* const* graphs, float* const* Y_d, const int32_t* n_iter,
+                                             const int32_t* tile_rows, int32_t count, const tsgne_params* p,
+                                             void* stream);
+
+/*
+ * Autotuner of per-graph tiles for tsgne_batch_run_tiles.  Graphs are grouped
+ * by size bucket b = floor(log2 n) (b < TSGNE_TILE_BUCKETS); every graph of a
+ * bucket takes the bucket's tile.  Buckets the cache fixes keep their tile;
+ * for the others it times `steps` batched steps of the whole batch (on scratch
+ * copies of Y_d, after a warm-up step) with one tile R in {2, 4, 8, 12, 16} for
+ * all of them, keeps the fastest, then, bucket by bucket (heaviest sum of n^2
+ * first), tries the other R for that bucket alone and keeps one that makes the
+ * batch at least 0.5 % faster.  tile_rows_out[count] receives each graph's
+ * tile; *ms_uniform and *ms_tuned (nullable) the ms per step with the best
+ * single tile and with the tuned tiles.  cache_path (nullable): a JSON file of
+ * {architecture: {bucket: tile rows}} (architecture as the device reports it,
+ * e.g. "gfx950"), read first and rewritten with the buckets tuned here.
+ * Leaves the graphs' workspaces planned for the last tile tried.
+ * Synchronising.  Errors: E_INVAL (also: the cache file cannot be written),
+ * E_NOMEM, E_DEVICE.
+ */
+#define TSGNE_TILE_BUCKETS 32
+TSGNE_API tsgne_status tsgne_autotune_tiles(tsgne_graph* const* graphs, const float* const* Y_d, int32_t count,
+                                            const tsgne_params* p, int32_t steps, const char* cache_path,
+                                            int32_t* tile_rows_out, double* ms_uniform, double* ms_tuned,
+                                            void* stream);
+
 /* ------------------------------------------------------------------------
  * Layout server: continuous batching of independent layout requests on the
  * current device.  Requests are copied in at submission and queued; a worker
@@ -476,10 +512,12 @@ TSGNE_API tsgne_status tsgne_autotune(tsgne_graph* const* graphs, const float* c
  * batched, graph-captured launch sequence (each request at its own step
  * index), and completes requests that reach n_iter (layout copied out, device
  * memory released).  With round_ms > 0 each round aims at that much GPU time
- * and gives every active request an equal share of it as steps (at least 1,
- * at most steps_per_round): small graphs take many steps per round, large ones
- * few, so small requests are not held back by large ones.  With round_ms <= 0
- * every active request takes steps_per_round steps per round.  Requests of
+ * and shares it out as steps (at least 1, at most steps_per_round) by
+ * rest_policy: by default requests with little work left go first and long
+ * ones run one at a time in submission order, so small requests are not held
+ * back by large ones and no large one finishes much later than it would alone
+ * in submission order.  With round_ms <= 0 every active request takes
+ * steps_per_round steps per round.  Requests of
  * different tile sizes form separate batched plans that run on parallel
  * branches of the round.  Each request's arithmetic depends only on itself
  * and its tile rows: its layout equals tsgne_run of the same graph alone with
@@ -493,15 +531,16 @@ typedef struct tsgne_server_config {
   int64_t hbm_budget;      /* device bytes the server may hold; 0 = 80 % of the free memory */
   int32_t max_active;      /* requests advanced together (default 64) */
   int32_t max_queue;       /* waiting requests before submit returns E_BUSY */
-  int32_t steps_per_round; /* most steps a request takes per round (default 64) */
+  int32_t steps_per_round; /* most steps a request takes per round (default 512) */
   int32_t tile_rows;       /* repulsion tile rows: 0 (default) = per request, the single-graph plan's choice
                               (its layout equals its own tsgne_run); 1, 2, 4, 8, 12, 14, 15 or 16 = for every
                               request */
   tsgne_params params;     /* optimiser; its exaggeration/momentum schedule applies to every request */
-  float round_ms;          /* target GPU time per round for the equal-share policy (default 25); <= 0: lockstep */
-  float oldest_share;      /* fraction of each round's time given to the oldest active request, the rest shared
-                              by rest_policy (default 0.5; 0 = the whole round by rest_policy); bounds how far
-                              small arrivals can slow the request that has waited longest */
+  float round_ms;          /* target GPU time per round (default 25); <= 0: lockstep */
+  float oldest_share;      /* TSGNE_SHARE_EQUAL and TSGNE_SHARE_SMALLEST_FIRST: fraction of each round's time
+                              given to the oldest active request, the rest shared by rest_policy (default 0.5;
+                              0 = the whole round by rest_policy); bounds how far small arrivals can slow the
+                              request that has waited longest */
   int32_t rest_policy;     /* how a round is shared: TSGNE_SHARE_SHORT_FIRST (default): requests with at most
                               long_ms of GPU time left take what they need first (least remaining first), and
                               long requests run one at a time in submission order with the rest (the others

@@ -131,6 +131,9 @@ class BatchRun {
 tsgne_status run_batch_steps(const BatchRun& br, const tsgne_params* p, int32_t n_steps, int32_t chunk,
                              hipStream_t s);
 
+// Distinct repulsion tile sizes (1, 2, 4, 8, 12, 14, 15, 16).
+constexpr int kMaxTileKinds = 8;
+
 // Event-pair timing of kernel phases (see tsgne_graph_set_timing).
 struct PhaseTimer {
   struct Pending {

@@ -44,7 +44,8 @@ EXPORTED = (
     "tsgne_shortest_path_embedding", "tsgne_kmeans", "tsgne_nmi", "tsgne_aq", "tsgne_build_P",
     "tsgne_build_P_walks", "tsgne_locality_order", "tsgne_permute_graph", "tsgne_permute_rows",
     "tsgne_graph_from_host_P", "tsgne_graph_free", "tsgne_graph_info", "tsgne_graph_export", "tsgne_gradient", "tsgne_step", "tsgne_run",
-    "tsgne_kl", "tsgne_kl_noalloc", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune", "tsgne_graph_set_timing", "tsgne_graph_timing",
+    "tsgne_kl", "tsgne_kl_noalloc", "tsgne_attraction", "tsgne_batch_run", "tsgne_autotune",
+    "tsgne_batch_run_tiles", "tsgne_autotune_tiles", "tsgne_graph_set_timing", "tsgne_graph_timing",
     "tsgne_server_config_default", "tsgne_server_create", "tsgne_server_submit", "tsgne_server_poll",
     "tsgne_server_wait", "tsgne_server_latency", "tsgne_server_error", "tsgne_server_release", "tsgne_server_cancel", "tsgne_server_get_stats",
     "tsgne_server_destroy", "tsgne_shard_create", "tsgne_shard_info", "tsgne_shard_repulsion", "tsgne_shard_set_timing",
@@ -164,6 +165,11 @@ def lib():
             "tsgne_batch_run": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32), i32, P, vp]),
             "tsgne_autotune": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_double), vp]),
+            "tsgne_batch_run_tiles": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32), i32, P, vp]),
+            "tsgne_autotune_tiles": (st, [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, P, i32, ctypes.c_char_p,
+                                          ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), vp]),
             "tsgne_server_config_default": (None, [ctypes.POINTER(tsgne_server_config)]),
             "tsgne_server_create": (st, [ctypes.POINTER(tsgne_server_config), ctypes.POINTER(vp)]),
             "tsgne_server_submit": (st, [vp, ctypes.POINTER(tsgne_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -616,22 +622,57 @@ def tsgne_autotune(graphs, Ys, params: tsgne_params, steps: int = 3, stream=None
     return best.value, list(ms)
 
 
+def tsgne_batch_run_tiles(graphs, Ys, n_iter, tile_rows, params: tsgne_params, stream=None) -> None:
+    """tsgne_batch_run with a tile per graph (tile_rows[k]; 0 = the single-graph plan's choice)."""
+    import torch
+    count = len(graphs)
+    if len(Ys) != count or len(n_iter) != count or len(tile_rows) != count:
+        raise ValueError("graphs, Ys, n_iter and tile_rows must have the same length")
+    for g, Y in zip(graphs, Ys):
+        _require(Y, torch.float32, (g.info()[0], 2), "Y")
+    hs = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+    ys = (ctypes.c_void_p * count)(*[Y.data_ptr() for Y in Ys])
+    it = (ctypes.c_int32 * count)(*[int(k) for k in n_iter])
+    tr = (ctypes.c_int32 * count)(*[int(k) for k in tile_rows])
+    _check(lib().tsgne_batch_run_tiles(hs, ys, it, tr, count, ctypes.byref(params), _stream(stream)))
+
+
+def tsgne_autotune_tiles(graphs, Ys, params: tsgne_params, steps: int = 3, cache_path: str | None = None,
+                         stream=None) -> tuple[list, float, float]:
+    """(tile rows per graph, ms per step with the best single tile, ms per step tuned): tiles by size
+    bucket floor(log2 n), cached by architecture in cache_path (JSON) when given."""
+    count = len(graphs)
+    hs = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+    ys = (ctypes.c_void_p * count)(*[Y.data_ptr() for Y in Ys])
+    out = (ctypes.c_int32 * count)()
+    mu, mt = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().tsgne_autotune_tiles(hs, ys, count, ctypes.byref(params), int(steps),
+                                      cache_path.encode() if cache_path else None, out, ctypes.byref(mu),
+                                      ctypes.byref(mt), _stream(stream)))
+    return list(out), mu.value, mt.value
+
+
 class Server:
     """Continuous-batching layout server (tsgne_server_*).  Requests are host
     numpy arrays; the server copies them in at submission."""
 
-    def __init__(self, hbm_budget: int = 0, max_active: int = 64, max_queue: int = 1 << 20,
-                 steps_per_round: int = 64, tile_rows: int = 0, params: tsgne_params | None = None,
-                 round_ms: float = 25.0, oldest_share: float | None = None, rest_policy: int | None = None,
+    def __init__(self, hbm_budget: int = 0, max_active: int | None = None, max_queue: int | None = None,
+                 steps_per_round: int | None = None, tile_rows: int = 0, params: tsgne_params | None = None,
+                 round_ms: float | None = None, oldest_share: float | None = None, rest_policy: int | None = None,
                  long_ms: float | None = None, short_share: float | None = None):
+        # arguments left at None keep tsgne_server_config_default's values
         cfg = tsgne_server_config()
         lib().tsgne_server_config_default(ctypes.byref(cfg))
         cfg.hbm_budget = int(hbm_budget)
-        cfg.max_active = int(max_active)
-        cfg.max_queue = int(max_queue)
-        cfg.steps_per_round = int(steps_per_round)
+        if max_active is not None:
+            cfg.max_active = int(max_active)
+        if max_queue is not None:
+            cfg.max_queue = int(max_queue)
+        if steps_per_round is not None:
+            cfg.steps_per_round = int(steps_per_round)
         cfg.tile_rows = int(tile_rows)
-        cfg.round_ms = float(round_ms)
+        if round_ms is not None:
+            cfg.round_ms = float(round_ms)
         if oldest_share is not None:
             cfg.oldest_share = float(oldest_share)
         if rest_policy is not None:

@@ -114,3 +114,72 @@ def test_full_batch_workload_sampled(gpu):
     assert err <= 1e-4, (gi.n, err)
     for g in graphs:
         g.close()
+
+
+def test_batch_with_per_graph_tiles_equals_alone_bitwise(gpu):
+    """Graphs of one batch with different tiles (explicit, and 0 = each
+    graph's single-graph plan): the tile groups run side by side, and every
+    graph equals its own tsgne_run with its tile, bit for bit."""
+    import torch
+    gis = small_batch(3) + [synth.small_sbm(n, 4, 6.0, 8, 390 + k) for k, n in enumerate([12_500, 5200])]
+    graphs = [upload(gi, gpu) for gi in gis]
+    n_iter = [60, 35, 51, 60, 7, 26, 40, 31]
+    tiles = [1, 2, 4, 8, 12, 16, 0, 0]
+    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0,
+                                   repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC)
+    Ys = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    tsgne.tsgne_batch_run_tiles(graphs, Ys, n_iter, tiles, p)
+    for gi, g, Yb, k, R in zip(gis, graphs, Ys, n_iter, tiles):
+        Ya = torch.from_numpy(gi.Y0).to(gpu)
+        pa = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0, tile_rows=R,
+                                        repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC)
+        tsgne.tsgne_run(g, Ya, k, pa)
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yb), (gi.n, R)
+    with pytest.raises(tsgne.TsgneError) as e:
+        tsgne.tsgne_batch_run_tiles(graphs, Ys, n_iter, [3] + tiles[1:], p)
+    assert e.value.status == tsgne.TSGNE_E_INVAL
+
+
+def test_autotune_tiles_by_bucket_and_cache(gpu, tmp_path):
+    """The bucket autotuner returns one supported tile per size bucket, leaves
+    the layouts alone, writes its choices to the cache under this device's
+    architecture, and takes cached buckets as given on the next call; the
+    tuned batch equals the graphs run alone with those tiles."""
+    import json
+    import math
+
+    import torch
+    gis = small_batch(4) + [synth.small_sbm(n, 4, 6.0, 8, 400 + k) for k, n in enumerate([9000, 17_000])]
+    graphs = [upload(gi, gpu) for gi in gis]
+    p = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0)
+    Ys = [torch.from_numpy(gi.Y0).to(gpu) for gi in gis]
+    before = [Y.clone() for Y in Ys]
+    cache = str(tmp_path / "tiles.json")
+    tiles, ms_u, ms_t = tsgne.tsgne_autotune_tiles(graphs, Ys, p, steps=2, cache_path=cache)
+    assert all(torch.equal(a, b) for a, b in zip(Ys, before))
+    assert all(t in (2, 4, 8, 12, 16) for t in tiles)
+    bucket = [int(math.floor(math.log2(gi.n))) for gi in gis]
+    for b in set(bucket):
+        assert len({t for t, bb in zip(tiles, bucket) if bb == b}) == 1
+    assert 0 < ms_t <= ms_u
+    saved = json.load(open(cache))
+    assert len(saved) == 1
+    arch, table = next(iter(saved.items()))
+    assert arch.startswith("gfx")
+    assert {int(k): v for k, v in table.items()} == {b: t for b, t in zip(bucket, tiles)}
+    # the cache fixes every bucket now: rewrite it to other tiles and they are used
+    forced = {str(b): 4 for b in set(bucket)}
+    json.dump({arch: forced, "gfx000": {"3": 8}}, open(cache, "w"))
+    tiles2, _, _ = tsgne.tsgne_autotune_tiles(graphs, Ys, p, steps=1, cache_path=cache)
+    assert tiles2 == [4] * len(gis)
+    assert json.load(open(cache))["gfx000"] == {"3": 8}
+    n_iter = [30] * len(gis)
+    tsgne.tsgne_batch_run_tiles(graphs, Ys, n_iter, tiles, p)
+    for gi, g, Yb, R in zip(gis, graphs, Ys, tiles):
+        Ya = torch.from_numpy(gi.Y0).to(gpu)
+        pa = tsgne.tsgne_params_default(exaggeration_iters=20, learning_rate=40.0, tile_rows=R,
+                                        repulsion=tsgne.TSGNE_REPULSION_SYMMETRIC)
+        tsgne.tsgne_run(g, Ya, 30, pa)
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yb), (gi.n, R)
