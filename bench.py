@@ -39,8 +39,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FM
 FLOP_PER_PAIR = 13                # algorithmic flops per ordered pair of the repulsion
 FP32_NONPACKED_FMA_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz (packed FP32 disabled)
 # FP32 flop the hardware counts per unordered pair in the symmetric repulsion
-# (rocprofv3 SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes / unordered pairs, FMA = 2)
-EXECUTED_FLOP_PER_UNORDERED_PAIR = 17.17
+# (rocprofv3 SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes / unordered pairs, FMA = 2;
+# 15 rows per lane, the 300K tile; 17.17 with 14 rows)
+EXECUTED_FLOP_PER_UNORDERED_PAIR = 17.165
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 

@@ -840,14 +840,15 @@ RepulsionPlan make_plan(int32_t n, int32_t R, int32_t variant) {
     // Cost model: the tiles (one wave each) of the busiest SIMD, i.e. the
     // tile count over the chip's 1024 SIMDs rounded up, times the tile area,
     // divided by the per-pair efficiency of that tile relative to R = 16
-    // (measured on MI355X at 300K nodes: 1 for R = 12..16, 0.97 for 8, 0.81
-    // for 4).  A SIMD needs about 64 / R resident tiles (64 independent pairs
-    // per step over its waves) to hide the dependent-issue latency, so fewer
-    // tiles than that take as long as that many.  Small graphs get small
-    // tiles (every SIMD busy), large graphs the tile whose count divides best
-    // over the SIMDs.
+    // (measured on MI355X as tile-pair slots per second of the repulsion at
+    // 200K-500K nodes, where every SIMD holds 19 or more tiles: 1.004 for
+    // R = 15, 0.996 for 14, 0.997 for 12, 0.969 for 8, 0.827 for 4).  A SIMD
+    // needs about 64 / R resident tiles (64 independent pairs per step over
+    // its waves) to hide the dependent-issue latency, so fewer tiles than that
+    // take as long as that many.  Small graphs get small tiles (every SIMD
+    // busy), large graphs the tile whose count divides best over the SIMDs.
     const int32_t rs[6] = {16, 15, 14, 12, 8, 4};
-    const double eff[6] = {1.0, 1.0, 1.0, 1.0, 0.97, 0.81};
+    const double eff[6] = {1.0, 1.004, 0.996, 0.997, 0.969, 0.827};
     double best = 0.0;
     for (int k = 0; k < 6; ++k) {
       const double T = (double)(kWave * rs[k]);

@@ -122,9 +122,9 @@ def test_argument_validation_before_device_work():
 def test_repulsion_plan_on_the_host():
     # the automatic tile follows the measured crossovers: 1 row per lane up to
     # 3,500 nodes, 2 up to 11,000, then the tiles-per-SIMD cost model
-    # (14 rows at the 300K benchmark graph, 15 at 1M and 3M)
+    # (15 rows at the 300K benchmark graph, 1M and 3M; 12 at 150K, 16 at 400K)
     for n, R in [(1, 1), (2000, 1), (3500, 1), (3501, 2), (11000, 2), (20000, 4), (100000, 8),
-                 (300000, 14), (1000000, 15), (3000000, 15)]:
+                 (150000, 12), (300000, 15), (400000, 16), (1000000, 15), (3000000, 15)]:
         r, tiles, nbytes = tsgne.tsgne_repulsion_plan(n)
         assert r == R, (n, r)
         nb = -(-n // (64 * r))
@@ -133,8 +133,8 @@ def test_repulsion_plan_on_the_host():
     # a fixed tile and the direct kernel (the whole square of tiles)
     r, tiles, nbytes = tsgne.tsgne_repulsion_plan(5000, 8, tsgne.TSGNE_REPULSION_DIRECT)
     assert (r, tiles, nbytes) == (8, 100, 8 * 10 * 10 * 512)
-    # partial buffers as the design states them: about 0.8 GB at 300K, 75 GB at 3M
-    assert abs(tsgne.tsgne_repulsion_plan(300000)[2] / 1e9 - 0.80) < 0.02
+    # partial buffers as the design states them: about 0.75 GB at 300K, 75 GB at 3M
+    assert abs(tsgne.tsgne_repulsion_plan(300000)[2] / 1e9 - 0.75) < 0.02
     assert abs(tsgne.tsgne_repulsion_plan(3000000)[2] / 1e9 - 75.0) < 0.5
     for bad in [(0, 0), (100, 3), (100, 32)]:
         with pytest.raises(tsgne.TsgneError) as e:
