@@ -271,6 +271,15 @@ def by_size_decile(sizes, st):
     return out
 
 
+def slowest(st, sizes, arrivals, top=3):
+    """The `top` slowest requests: submission index, nodes, arrival (s),
+    latency and wait for admission (ms)."""
+    lat = st["per_request"]
+    order = sorted(range(len(lat)), key=lambda k: -lat[k][0])[:top]
+    return [{"request": k, "nodes": int(sizes[k]), "arrival_s": round(float(arrivals[k]), 3),
+             "latency_ms": lat[k][0], "queued_ms": lat[k][1]} for k in order]
+
+
 def stream_summary(st, wall, count):
     return {"layouts_per_s": count / wall, "latency_p50_ms": st["latency_p50_ms"],
             "latency_p99_ms": st["latency_p99_ms"], "latency_mean_ms": st["latency_mean_ms"],
@@ -298,6 +307,7 @@ def serving_leg(reqs, n_iter):
     a time."""
     specs = [None] * len(reqs)
     count = len(reqs)
+    sizes = [g.n for g in reqs]
     kw = serve_kwargs(n_iter)
     kw1 = dict(kw, max_active=1)
     st_sat, wall_sat = serve_stream(kw, specs, [0.0] * count, n_iter, reqs=reqs)
@@ -315,7 +325,8 @@ def serving_leg(reqs, n_iter):
         "policy": "short-first: short requests first, long ones one at a time in submission order",
         "saturated_layouts_per_s": sat_rate, "saturated_one_at_a_time_layouts_per_s": count / wall_sat1,
         "saturated_speedup": wall_sat1 / wall_sat, "qps": 0.8 * sat_rate,
-        "batched": stream_summary(st, wall, count), "one_at_a_time": stream_summary(st1, wall1, count),
+        "batched": dict(stream_summary(st, wall, count), slowest=slowest(st, sizes, arrivals)),
+        "one_at_a_time": dict(stream_summary(st1, wall1, count), slowest=slowest(st1, sizes, arrivals)),
         "note": "served figures include host-to-device copies of each request and the copy of each layout back",
     }
 
@@ -378,7 +389,8 @@ def run_serve(args) -> int:
         st, wall = serve_stream(configs[name], specs, arrivals, n_iter, pool, label=name)
         log("%s at %.2f req/s: p50 %.0f ms, p99 %.0f ms, %.2f layouts/s" %
             (name, qps, st["latency_p50_ms"], st["latency_p99_ms"], count / wall))
-        result[name] = dict(stream_summary(st, wall, count), by_size_decile=by_size_decile(sizes, st))
+        result[name] = dict(stream_summary(st, wall, count), by_size_decile=by_size_decile(sizes, st),
+                            slowest=slowest(st, sizes, arrivals))
         if name == runs[0]:
             result["value"] = count / wall
             result["ms_per_step"] = wall * 1e3
