@@ -292,10 +292,23 @@ tsgne_status ensure_workspace(tsgne_graph* g, const tsgne_params* p) {
   free_workspace(ws);
   ws.plan = want;
   const RepulsionPlan& pl = ws.plan;
+  // Symmetric plans dispatch the diagonal tiles (one resident row per lane
+  // per pass, the slower kind) first, then the off-diagonal tiles row by row,
+  // and last the tiles against the last block (a, nb - 1), which is partly
+  // filled when T does not divide n: the launch's tail is made of its
+  // shortest tiles.  A tile's position in this list is also its Z partial's
+  // slot, i.e. Z's summation order.
   std::vector<int2> items;
   items.reserve((size_t)pl.items);
-  for (int32_t a = 0; a < pl.nb; ++a)
-    for (int32_t b = (pl.variant == TSGNE_REPULSION_DIRECT ? 0 : a); b < pl.nb; ++b) items.push_back(make_int2(a, b));
+  if (pl.variant == TSGNE_REPULSION_DIRECT) {
+    for (int32_t a = 0; a < pl.nb; ++a)
+      for (int32_t b = 0; b < pl.nb; ++b) items.push_back(make_int2(a, b));
+  } else {
+    for (int32_t a = 0; a < pl.nb; ++a) items.push_back(make_int2(a, a));
+    for (int32_t a = 0; a < pl.nb; ++a)
+      for (int32_t b = a + 1; b < pl.nb - 1; ++b) items.push_back(make_int2(a, b));
+    for (int32_t a = 0; a < pl.nb - 1; ++a) items.push_back(make_int2(a, pl.nb - 1));
+  }
   const size_t part_len = (size_t)pl.nb * pl.nb * pl.T;
   ws.kl_blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1024, (g->nnz + 255) / 256));
   hipError_t e = hipSuccess;

@@ -34,7 +34,7 @@ tsgne_status BatchRun::setup(const BatchMember* m, int32_t count, int32_t R, con
   bp_.R = R;
   bp_.T = kWave * R;
   std::vector<BatchDesc> descs((size_t)count);
-  std::vector<int4> diag_items, items;
+  std::vector<int4> diag_items, items, last_items;
   std::vector<int2> chunks, heavy, blocks;
   for (int32_t k = 0; k < count; ++k) {
     tsgne_graph* g = m[k].g;
@@ -58,10 +58,16 @@ tsgne_status BatchRun::setup(const BatchMember* m, int32_t count, int32_t R, con
     d.nb = ws.plan.nb;
     d.n_iter = m[k].n_iter;
     d.eta = effective_eta(g, p);
-    // items in the graph's own order (the Z partial slot is the local index)
-    int64_t li = 0;
-    for (int32_t a = 0; a < ws.plan.nb; ++a)
-      for (int32_t b = a; b < ws.plan.nb; ++b, ++li) (a == b ? diag_items : items).push_back(make_int4(k, a, b, (int)li));
+    // each tile's Z partial slot is its index in the graph's own list
+    // (diagonal tiles first, then the off-diagonal ones row by row, the tiles
+    // against the last block last)
+    const int32_t nb = ws.plan.nb;
+    int64_t li = nb;
+    for (int32_t a = 0; a < nb; ++a) {
+      diag_items.push_back(make_int4(k, a, a, a));
+      for (int32_t b = a + 1; b < nb - 1; ++b, ++li) items.push_back(make_int4(k, a, b, (int)li));
+    }
+    for (int32_t a = 0; a < nb - 1; ++a, ++li) last_items.push_back(make_int4(k, a, nb - 1, (int)li));
     for (int32_t r = 0; r < g->n; r += kBatchAttractRows) chunks.push_back(make_int2(k, r));
     for (int32_t r = 0; r < g->n; r += kBatchBlockRows) blocks.push_back(make_int2(k, r));
     if (g->n_heavy > 0) {
@@ -70,8 +76,10 @@ tsgne_status BatchRun::setup(const BatchMember* m, int32_t count, int32_t R, con
       for (int32_t r : h) heavy.push_back(make_int2(k, r));
     }
   }
-  // diagonal tiles (one row per lane per pass, the slower kind) go first
+  // diagonal tiles (one row per lane per pass, the slower kind) go first,
+  // the tiles against each graph's partly filled last block last
   diag_items.insert(diag_items.end(), items.begin(), items.end());
+  diag_items.insert(diag_items.end(), last_items.begin(), last_items.end());
   bp_.n_items = (int64_t)diag_items.size();
   bp_.n_light_chunks = (int32_t)chunks.size();
   bp_.n_heavy = (int32_t)heavy.size();

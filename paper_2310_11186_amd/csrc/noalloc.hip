@@ -43,14 +43,25 @@ hipError_t scratch_address(int dev, char** out) {
 
 constexpr int kFillThreads = 256;
 
-// Tile list of a plan: row block a (one workgroup) writes its tiles (a, b),
-// b from a (symmetric) or 0 (direct) to nb - 1, at the position the host's
-// list gives them (row-major over the triangle or the square).
+// Tile list of a plan, in the order of the host's list: direct plans row by
+// row over the square; symmetric plans the nb diagonal tiles (a, a) first,
+// then the tiles (a, a < b < nb - 1) row by row, then the tiles (a, nb - 1).
+// Row block a (one workgroup) writes its own tiles.
 __global__ __launch_bounds__(kFillThreads) void k_fill_items(int32_t nb, int symmetric, int2* __restrict__ items) {
   const int32_t a = blockIdx.x;
-  const int64_t first = symmetric ? (int64_t)a * nb - (int64_t)a * (a - 1) / 2 : (int64_t)a * nb;
-  const int32_t b0 = symmetric ? a : 0;
-  for (int32_t b = b0 + (int32_t)threadIdx.x; b < nb; b += kFillThreads) items[first + (b - b0)] = make_int2(a, b);
+  if (!symmetric) {
+    for (int32_t b = (int32_t)threadIdx.x; b < nb; b += kFillThreads) items[(int64_t)a * nb + b] = make_int2(a, b);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    items[a] = make_int2(a, a);
+    // after the nb diagonal and the (nb - 1)(nb - 2) / 2 inner tiles
+    if (a < nb - 1) items[nb + (int64_t)(nb - 1) * (nb - 2) / 2 + a] = make_int2(a, nb - 1);
+  }
+  // rows before a hold (nb - 2 - 0) + ... + (nb - 2 - (a - 1)) inner tiles
+  const int64_t first = nb + (int64_t)a * (nb - 2) - (int64_t)a * (a - 1) / 2;
+  for (int32_t b = a + 1 + (int32_t)threadIdx.x; b < nb - 1; b += kFillThreads)
+    items[first + (b - a - 1)] = make_int2(a, b);
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
