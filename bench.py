@@ -919,6 +919,9 @@ def main() -> int:
         "roofline": {
             "bound": "alu",
             "kernel": "k_repulse (all-pairs repulsion + Z partials)",
+            "instantiation": repulse_kernel_name(tsgne.tsgne_repulsion_plan(gi.n, args.tile_rows, rep)[0],
+                                                 prec == tsgne.TSGNE_PREC_SPLIT,
+                                                 rep != tsgne.TSGNE_REPULSION_DIRECT),
             "achieved": achieved_tflops,
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
