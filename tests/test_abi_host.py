@@ -83,6 +83,19 @@ def test_argument_validation_before_device_work():
     assert L.tsgne_run(None, dummy, 10, ctypes.byref(p), None, None) == tsgne.TSGNE_E_INVAL
     k = ctypes.c_double(0)
     assert L.tsgne_kl(None, dummy, ctypes.byref(k), None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_kl_noalloc(None, dummy, dummy, None) == tsgne.TSGNE_E_INVAL
+    # batches with a tile per graph: null arrays, an empty batch, no steps to time
+    one = (ctypes.c_void_p * 1)(None)
+    it = (ctypes.c_int32 * 1)(10)
+    assert L.tsgne_batch_run_tiles(None, one, it, it, 1, ctypes.byref(p), None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_batch_run_tiles(one, one, it, it, 0, ctypes.byref(p), None) == tsgne.TSGNE_E_INVAL
+    assert L.tsgne_batch_run_tiles(one, one, it, it, 1, ctypes.byref(p), None) == tsgne.TSGNE_E_INVAL   # null graph
+    ms = ctypes.c_double(0)
+    assert L.tsgne_autotune_tiles(one, one, 1, ctypes.byref(p), 3, None, None, ctypes.byref(ms), ctypes.byref(ms),
+                                  None) == tsgne.TSGNE_E_INVAL                                       # no output
+    assert L.tsgne_autotune_tiles(one, one, 1, ctypes.byref(p), 0, None, it, None, None, None) == tsgne.TSGNE_E_INVAL
+    buf = ctypes.create_string_buffer(16)
+    assert L.tsgne_server_error(None, 1, buf, 16) == tsgne.TSGNE_E_INVAL
     lv = ctypes.c_int32(7)
     sp = L.tsgne_shortest_path_embedding
     assert sp(5, 4, dummy, dummy, 0, dummy, 2.0, dummy, ctypes.byref(lv), None) == tsgne.TSGNE_E_INVAL   # d < 1
