@@ -152,10 +152,11 @@ std::vector<int2> shard_tiles(int32_t n, int32_t R, int32_t shard, int32_t n_sha
 // Tile rows for a shard: the single-graph cost model applied to the largest
 // shard's tile count (its tiles over the chip's 1024 SIMDs rounded up, at
 // least the 64 / R a SIMD needs to hide latency, times the tile area, over
-// the tile's per-pair efficiency relative to R = 16).
+// the tile's per-pair efficiency relative to R = 16, the values the
+// single-graph plan uses: measured on MI355X at 200K-500K nodes).
 int32_t shard_tile_rows(int32_t n, int32_t n_shards) {
   const int32_t rs[6] = {16, 15, 14, 12, 8, 4};
-  const double eff[6] = {1.0, 1.0, 1.0, 1.0, 0.97, 0.81};
+  const double eff[6] = {1.0, 1.004, 0.996, 0.997, 0.969, 0.827};
   constexpr int64_t kSimds = 1024;
   double best = 0.0;
   int32_t R = 8;
