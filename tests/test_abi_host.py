@@ -177,3 +177,22 @@ def test_traffic_is_reported_only_for_the_counted_kernel():
         assert bench.measured_traffic("dcsbm300k", rec["kernel"]) == rec["bytes_per_launch"]
     else:
         assert bench.measured_traffic("dcsbm300k", rec["kernel"]) is None
+
+
+def test_serving_summaries():
+    """The serving statistics bench.py reports: nearest-rank percentiles (the
+    server's own definition), size deciles and the slowest requests."""
+    import bench
+    assert bench.nearest_rank([5, 1, 3, 2, 4], 0.5) == 3
+    assert bench.nearest_rank(list(range(1, 201)), 0.99) == 198        # 200 values: the third largest
+    assert bench.nearest_rank(list(range(1, 49)), 0.99) == 48          # 48 values: the largest
+    assert bench.nearest_rank([], 0.5) is None
+    sizes = list(range(100, 0, -5))                                    # 20 requests, largest first
+    st = {"per_request": [(float(s), 0.5 * s) for s in sizes]}          # latency grows with size
+    dec = bench.by_size_decile(sizes, st)
+    assert [d["requests"] for d in dec] == [2] * 10
+    assert dec[0]["nodes"] == [5, 10] and dec[-1]["nodes"] == [95, 100]
+    assert dec[-1]["latency_max_ms"] == 100.0
+    slow = bench.slowest(st, sizes, [0.1 * k for k in range(20)], top=3)
+    assert [x["request"] for x in slow] == [0, 1, 2]
+    assert slow[0]["nodes"] == 100 and slow[0]["queued_ms"] == 50.0 and slow[1]["arrival_s"] == 0.1
